@@ -1,0 +1,376 @@
+"""Plain FP64 CPU oracle for the vdW-DF nonlocal correlation energy and potential, evaluated
+in the Roman-Perez--Soler (RPS) form of the libvdwxc paper (arXiv:1703.06999).
+
+TEST INFRASTRUCTURE ONLY.  This module is the independent reference that the GPU library is
+checked against.  Only the test-suite, the package's smoke check and the CPU-baseline leg of the
+benchmark may import it; the library never does, and it shares no code with the library (it
+reads the same seeded inputs and kernel table, nothing else).
+
+It is written for clarity, not speed: every step is the paper's step, in its order and notation,
+with numpy / scipy.fft as the only library primitives (the FFT is a library routine; it is pinned
+against a naive DFT in the tests).
+
+Steps (Sec. 3, Table 1, and the enumerated procedure of Sec. 3):
+  1. q0(n, sigma) with the saturation h_a                       (appendix)
+  2. theta_a(r) = n(r) p_a(q0(r))                               (Sec. 2, helper splines)
+  3. theta_a(k) by forward 3D FFT                               (Sec. 3, step 2)
+  4. per k: phi_ab(|k|) by linear interpolation in k; F_a(k) = sum_b phi_ab theta_b(k);
+     energy sum_a theta_a*(k) F_a(k)                            (Sec. 3, steps 3a-3c; eq. enlk)
+  5. F_a(r) by inverse FFT                                      (Sec. 3, step 4)
+  6. dE/dn, dE/dsigma                                           (Sec. 2, eqs. dedn and dedsigma)
+
+Readings where the paper is silent or garbled (each also listed in the design notes):
+  * r_s = (3/(4 pi n))^{1/3}, the Wigner-Seitz radius (the appendix prints r_s^3 = 4 pi n/3,
+    which inverts it).
+  * The gradient term of q0 is -(Z_ab/36) sigma/(k_F n^2), as printed in the appendix's main
+    formula (q0 then carries units of inverse length, like k_F).
+  * Helper splines: natural cubic splines (second derivative zero at both ends).
+  * q0 below the first mesh point is clamped to it with zero derivatives; q0 equal to the last
+    mesh point falls in the last interval.
+  * Saturation: for x/a >= 2, exp(-S) underflows to zero in FP64, so h = a and h' = 0 exactly;
+    the derivative is set to zero there without forming 0 * (large).
+  * n < 1e-30 is a vacuum point: theta = 0 and both partial derivatives are zero.
+  * Discrete transforms: theta(m) = sum_j theta(r_j) exp(-2 pi i j.m/N) (unnormalised forward),
+    F(r) = (1/N) sum_m F(m) exp(+2 pi i j.m/N), E = Omega/(2 N^2) sum_m sum_a Re[theta_a* F_a];
+    this is eq. enlk with integrals replaced by the periodic-grid sums.
+  * |G| of a frequency that sits on the Nyquist index of an even axis is ambiguous (+N/2 and
+    -N/2 alias); |G|^2 is taken as the mean over the two aliases, i.e. the Nyquist part and
+    the rest are added in quadrature.  This keeps phi(|G|) even in G, so F(k) stays Hermitian
+    and F(r) real; for orthogonal cells it is the plain |G|.
+  * phi = 0 for |G| >= kmax of the table (callers reject such grids).
+  * Potential entry: v = dE/dn - div(2 dE/dsigma grad n), the divergence (and, when no gradient
+    is supplied, the gradient) taken spectrally with every Nyquist frequency zeroed.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+import scipy.fft as sfft
+
+# ---------------------------------------------------------------------------------------------
+# constants printed in the paper's appendix
+# ---------------------------------------------------------------------------------------------
+PW92_A = 0.031091
+PW92_ALPHA1 = 0.2137
+PW92_BETA = (7.5957, 3.5876, 1.6382, 0.49294)
+ZAB = {"DF1": -0.8491, "DF2": -1.887}
+SATURATION_A = 5.0
+SATURATION_TERMS = 12
+VACUUM_DENSITY = 1e-30
+
+WORKERS = os.cpu_count() or 1
+
+
+# ---------------------------------------------------------------------------------------------
+# 1. q0 (appendix)
+# ---------------------------------------------------------------------------------------------
+
+def pw92_correlation(rs):
+    """Perdew-Wang LDA correlation energy per particle eps_c(r_s) and d eps_c / d r_s.
+
+    eps_c = -2A (1 + alpha1 r_s) log[1 + 1/(2A sum_{i=1..4} beta_i r_s^{i/2})]   (appendix)
+    """
+    rs = np.asarray(rs, dtype=np.float64)
+    b1, b2, b3, b4 = PW92_BETA
+    sq = np.sqrt(rs)
+    Q = 2.0 * PW92_A * (b1 * sq + b2 * rs + b3 * rs * sq + b4 * rs * rs)
+    dQ = 2.0 * PW92_A * (0.5 * b1 / sq + b2 + 1.5 * b3 * sq + 2.0 * b4 * rs)
+    L = np.log1p(1.0 / Q)
+    eps = -2.0 * PW92_A * (1.0 + PW92_ALPHA1 * rs) * L
+    deps = -2.0 * PW92_A * PW92_ALPHA1 * L + 2.0 * PW92_A * (1.0 + PW92_ALPHA1 * rs) * dQ / (Q * Q + Q)
+    return eps, deps
+
+
+def saturation(x, a=SATURATION_A):
+    """h_a(x) = a [1 - exp(-sum_{m=1}^{12} (x/a)^m / m)] and its derivative h_a'(x)  (appendix)."""
+    x = np.asarray(x, dtype=np.float64)
+    t = x / a
+    S = np.zeros_like(t)
+    dS = np.zeros_like(t)          # dS/dx = (1/a) sum_{m=1}^{12} t^{m-1}
+    for m in range(1, SATURATION_TERMS + 1):
+        S = S + t ** m / m
+        dS = dS + t ** (m - 1)
+    e = np.exp(-S)
+    h = a * (1.0 - e)
+    saturated = t >= 2.0           # exp(-S) == 0 exactly in FP64 there
+    hprime = np.where(saturated, 0.0, e * np.where(saturated, 0.0, dS))
+    h = np.where(saturated, a, h)
+    return h, hprime
+
+
+def q0_unsaturated(n, sigma, zab):
+    """q0 = k_F - (4 pi/3) eps_c^LDA - (Z_ab/36) sigma/(k_F n^2) for n > 0, with its partial
+    derivatives in n and sigma (appendix)."""
+    n = np.asarray(n, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    kF = np.cbrt(3.0 * math.pi ** 2 * n)
+    rs = np.cbrt(3.0 / (4.0 * math.pi * n))
+    eps_c, deps_c = pw92_correlation(rs)
+    x = kF - (4.0 * math.pi / 3.0) * eps_c - (zab / 36.0) * sigma / (kF * n * n)
+    # d kF/dn = kF/(3n); d rs/dn = -rs/(3n)
+    dx_dn = (kF / (3.0 * n) + (4.0 * math.pi / 9.0) * (rs / n) * deps_c
+             + (7.0 * zab / 108.0) * sigma / (kF * n ** 3))
+    dx_dsigma = -(zab / 36.0) / (kF * n * n)
+    return x, dx_dn, dx_dsigma
+
+
+def q0_and_derivatives(n, sigma, qmesh, zab):
+    """Saturated q0 = h_5(q0_orig) with dq0/dn, dq0/dsigma and the vacuum mask (n < 1e-30)."""
+    n = np.asarray(n, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    vac = ~(n >= VACUUM_DENSITY)
+    ns = np.where(vac, 1.0, n)                      # any positive value; masked below
+    x, dx_dn, dx_ds = q0_unsaturated(ns, np.where(vac, 0.0, sigma), zab)
+    q0, hp = saturation(x)
+    dq_dn = np.where(hp == 0.0, 0.0, hp * np.where(hp == 0.0, 0.0, dx_dn))
+    dq_ds = np.where(hp == 0.0, 0.0, hp * np.where(hp == 0.0, 0.0, dx_ds))
+    below = q0 < qmesh[0]                           # clamp to the first mesh point
+    q0 = np.where(below, qmesh[0], q0)
+    dq_dn = np.where(below | vac, 0.0, dq_dn)
+    dq_ds = np.where(below | vac, 0.0, dq_ds)
+    return q0, dq_dn, dq_ds, vac
+
+
+# ---------------------------------------------------------------------------------------------
+# 2. helper splines and theta (Sec. 2)
+# ---------------------------------------------------------------------------------------------
+
+def spline_coefficients(qmesh):
+    """Coefficients a^c_{ab}, c = 0..3, of the helper splines p_a (Sec. 2):
+
+        p_a(q_b + dq) = sum_c a^c_{ab} dq^c,   0 <= dq < q_{b+1} - q_b,
+
+    fixed by p_a(q_b) = delta_ab and continuity of the first two derivatives; the two free end
+    conditions are taken natural (p_a'' = 0 at both ends).  Returns an array [4][M][M-1].
+    """
+    q = np.asarray(qmesh, dtype=np.float64)
+    M = q.shape[0]
+    h = np.diff(q)
+    coeffs = np.zeros((4, M, M - 1))
+    for a in range(M):
+        y = np.zeros(M)
+        y[a] = 1.0
+        # second derivatives m_b: tridiagonal system, m_0 = m_{M-1} = 0
+        A = np.zeros((M, M))
+        rhs = np.zeros(M)
+        A[0, 0] = 1.0
+        A[M - 1, M - 1] = 1.0
+        for b in range(1, M - 1):
+            A[b, b - 1] = h[b - 1]
+            A[b, b] = 2.0 * (h[b - 1] + h[b])
+            A[b, b + 1] = h[b]
+            rhs[b] = 6.0 * ((y[b + 1] - y[b]) / h[b] - (y[b] - y[b - 1]) / h[b - 1])
+        m = np.linalg.solve(A, rhs)
+        for b in range(M - 1):
+            coeffs[0, a, b] = y[b]
+            coeffs[1, a, b] = (y[b + 1] - y[b]) / h[b] - h[b] * (2.0 * m[b] + m[b + 1]) / 6.0
+            coeffs[2, a, b] = m[b] / 2.0
+            coeffs[3, a, b] = (m[b + 1] - m[b]) / (6.0 * h[b])
+    return coeffs
+
+
+def spline_interval(qmesh, q0):
+    """Interval b with q_b <= q0 < q_{b+1}; q0 equal to the last mesh point uses the last one."""
+    M = len(qmesh)
+    b = np.searchsorted(qmesh, q0, side="right") - 1
+    return np.clip(b, 0, M - 2)
+
+
+def spline_values(qmesh, coeffs, q0):
+    """p_a(q0) and p_a'(q0) for all a: arrays [M][...]."""
+    b = spline_interval(qmesh, q0)
+    dq = q0 - qmesh[b]
+    a0, a1, a2, a3 = (coeffs[c][:, b] for c in range(4))
+    p = a0 + a1 * dq + a2 * dq ** 2 + a3 * dq ** 3
+    dp = a1 + 2.0 * a2 * dq + 3.0 * a3 * dq ** 2
+    return p, dp
+
+
+def theta_and_derivatives(n, sigma, qmesh, zab):
+    """theta_a = n p_a(q0) (Sec. 2) and the factors of the partial derivatives (eqs. dedn,
+    dedsigma):  dtheta_a/dn = p_a + n p_a' dq0/dn,  dtheta_a/dsigma = n p_a' dq0/dsigma.
+    Vacuum points carry zeros.  Arrays [M][N1][N2][N3]."""
+    n = np.asarray(n, dtype=np.float64)
+    coeffs = spline_coefficients(qmesh)
+    q0, dq_dn, dq_ds, vac = q0_and_derivatives(n, sigma, qmesh, zab)
+    p, dp = spline_values(qmesh, coeffs, q0)
+    nn = np.where(vac, 0.0, n)
+    theta = nn * p
+    dtheta_dn = np.where(vac, 0.0, p + nn * dp * dq_dn)
+    dtheta_ds = nn * dp * dq_ds
+    return theta, dtheta_dn, dtheta_ds
+
+
+# ---------------------------------------------------------------------------------------------
+# grid geometry
+# ---------------------------------------------------------------------------------------------
+
+def reciprocal_vectors(cell):
+    """Rows b_i with a_i . b_j = 2 pi delta_ij."""
+    return 2.0 * math.pi * np.linalg.inv(np.asarray(cell, dtype=np.float64)).T
+
+
+def signed_frequencies(N):
+    """m -> m for m < N/2, m - N above; the Nyquist index N/2 of an even axis is flagged."""
+    m = np.arange(N)
+    mbar = np.where(m <= N // 2, m, m - N)
+    nyq = (N % 2 == 0) & (m == N // 2)
+    return mbar.astype(np.float64), nyq
+
+
+def gvector_norms(grid, cell):
+    """|G_m| for every m of the full grid, Nyquist components added in quadrature."""
+    B = reciprocal_vectors(cell)
+    freq = [signed_frequencies(N) for N in grid]
+    regular = np.zeros(tuple(grid) + (3,))
+    nyquist = np.zeros(tuple(grid) + (3,))
+    for i in range(3):
+        f, nyq = freq[i]
+        shape = [1, 1, 1]
+        shape[i] = grid[i]
+        fi = f.reshape(shape)
+        ni = nyq.reshape(shape)
+        regular += (np.where(ni, 0.0, fi))[..., None] * B[i]
+        nyquist += (np.where(ni, fi, 0.0))[..., None] * B[i]
+    g2 = np.sum(regular ** 2, axis=-1) + np.sum(nyquist ** 2, axis=-1)
+    return np.sqrt(g2)
+
+
+def gvectors_cartesian(grid, cell):
+    """Cartesian G_m (three arrays over the full grid) and the mask of frequencies that touch a
+    Nyquist index on any even axis."""
+    B = reciprocal_vectors(cell)
+    G = np.zeros((3,) + tuple(grid))
+    any_nyq = np.zeros(tuple(grid), dtype=bool)
+    for i in range(3):
+        f, nyq = signed_frequencies(grid[i])
+        shape = [1, 1, 1]
+        shape[i] = grid[i]
+        for c in range(3):
+            G[c] += f.reshape(shape) * B[i, c]
+        any_nyq |= nyq.reshape(shape)
+    return G, any_nyq
+
+
+# ---------------------------------------------------------------------------------------------
+# 3-5. FFTs and the k-space contraction (Sec. 3, steps 2-4; eq. enlk)
+# ---------------------------------------------------------------------------------------------
+
+def forward_fft(fields):
+    """theta(m) = sum_j theta(r_j) exp(-2 pi i j.m / N) over the last three axes."""
+    return sfft.fftn(fields, axes=(-3, -2, -1), workers=WORKERS)
+
+
+def inverse_fft(fields_k):
+    """F(r_j) = (1/N) sum_m F(m) exp(+2 pi i j.m / N), real part."""
+    return sfft.ifftn(fields_k, axes=(-3, -2, -1), workers=WORKERS).real
+
+
+def interpolate_kernel(table, kmax, knorm):
+    """phi_ab(k) from the tabulated phi_ab(k_j), k_j = j dk, by linear interpolation in k
+    (Sec. 3, step 3a); zero at and beyond kmax.  ``table`` [nk][M][M]; returns [len(k)][M][M]."""
+    nk = table.shape[0]
+    dk = kmax / (nk - 1)
+    s = knorm / dk
+    j = np.floor(s).astype(np.int64)
+    inside = knorm < kmax
+    j = np.where(inside, j, 0)
+    w = np.where(inside, s - j, 0.0)
+    j1 = np.minimum(j + 1, nk - 1)
+    phi = (1.0 - w)[:, None, None] * table[j] + w[:, None, None] * table[j1]
+    return np.where(inside[:, None, None], phi, 0.0)
+
+
+def kspace_contraction(theta_k, knorm, table, kmax, chunk=1 << 16):
+    """F_a(m) = sum_b phi_ab(|G_m|) theta_b(m) and the energy sum sum_m sum_a Re[theta_a* F_a]
+    (Sec. 3, steps 3a-3c).  theta_k: [M][...] complex; returns (F_k, energy_sum)."""
+    M = theta_k.shape[0]
+    th = theta_k.reshape(M, -1)
+    kn = knorm.reshape(-1)
+    F = np.empty_like(th)
+    esum = 0.0
+    for s in range(0, kn.shape[0], chunk):
+        phi = interpolate_kernel(table, kmax, kn[s:s + chunk])      # [c][a][b]
+        f = np.einsum("cab,bc->ac", phi, th[:, s:s + chunk])
+        F[:, s:s + chunk] = f
+        esum += float(np.sum((np.conj(th[:, s:s + chunk]) * f).real))
+    return F.reshape(theta_k.shape), esum
+
+
+# ---------------------------------------------------------------------------------------------
+# the whole evaluation
+# ---------------------------------------------------------------------------------------------
+
+def _as_table(kernel):
+    return np.asarray(kernel.table, dtype=np.float64), float(kernel.kmax), \
+        np.asarray(kernel.qmesh, dtype=np.float64)
+
+
+def check_inputs(grid, cell, n, sigma):
+    if any(int(g) < 1 for g in grid):
+        raise ValueError("grid sizes must be >= 1")
+    if np.linalg.det(np.asarray(cell, dtype=np.float64)) <= 0.0:
+        raise ValueError("cell must have positive volume (right-handed lattice vectors)")
+    if not (np.all(np.isfinite(n)) and np.all(np.isfinite(sigma))):
+        raise ValueError("density or sigma contains NaN/inf")
+
+
+def energy_and_partials(n, sigma, cell, kernel, flavour="DF1", return_intermediates=False):
+    """E_c^nl and the partial derivatives dE/dn, dE/dsigma as fields (Sec. 2, eqs. dedn and
+    dedsigma; Sec. 3 procedure).  Returns (E, dedn, dedsigma[, dict])."""
+    n = np.asarray(n, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    grid = n.shape
+    check_inputs(grid, cell, n, sigma)
+    table, kmax, qmesh = _as_table(kernel)
+    N = n.size
+    omega = float(np.linalg.det(np.asarray(cell, dtype=np.float64)))
+    knorm = gvector_norms(grid, cell)
+    if np.max(knorm) >= kmax:
+        raise ValueError("grid reaches |G| >= kmax of the kernel table")
+
+    theta, dth_dn, dth_ds = theta_and_derivatives(n, sigma, qmesh, ZAB[flavour])   # step 1
+    theta_k = forward_fft(theta)                                                    # step 2
+    F_k, esum = kspace_contraction(theta_k, knorm, table, kmax)                    # step 3
+    E = omega / (2.0 * N * N) * esum
+    F = inverse_fft(F_k)                                                            # step 4
+    dedn = np.sum(F * dth_dn, axis=0)                                               # step 5
+    dedsigma = np.sum(F * dth_ds, axis=0)
+    if return_intermediates:
+        return E, dedn, dedsigma, dict(theta=theta, theta_k=theta_k, F_k=F_k, F=F,
+                                       dtheta_dn=dth_dn, dtheta_dsigma=dth_ds, knorm=knorm)
+    return E, dedn, dedsigma
+
+
+def energy_real_space(theta, F, cell):
+    """E = (dV/2) sum_j sum_a theta_a(r_j) F_a(r_j): the real-space form of Sec. 2."""
+    N = theta[0].size
+    dV = float(np.linalg.det(np.asarray(cell, dtype=np.float64))) / N
+    return 0.5 * dV * float(np.sum(theta * F))
+
+
+def spectral_derivative(f, cell, axis):
+    """D_i f: derivative along Cartesian axis i by FFT, multiply by i G_i, inverse FFT, with every
+    frequency that touches a Nyquist index set to zero.  Real and antisymmetric."""
+    G, any_nyq = gvectors_cartesian(f.shape, cell)
+    fk = sfft.fftn(f, workers=WORKERS)
+    dk = np.where(any_nyq, 0.0, 1j * G[axis] * fk)
+    return sfft.ifftn(dk, workers=WORKERS).real
+
+
+def spectral_gradient(n, cell):
+    return np.stack([spectral_derivative(n, cell, i) for i in range(3)])
+
+
+def potential(n, cell, kernel, grad=None, flavour="DF1"):
+    """v_c^nl = dE/dn|_sigma - div(2 dE/dsigma grad n)  (Sec. 2: v = dE/dn + dE/dsigma dsigma/dn,
+    with sigma = |grad n|^2).  ``grad`` [3][...] is the supplied gradient; None means the
+    spectral gradient of n.  Returns (E, v, dedn, dedsigma)."""
+    n = np.asarray(n, dtype=np.float64)
+    g = spectral_gradient(n, cell) if grad is None else np.asarray(grad, dtype=np.float64)
+    sigma = np.sum(g * g, axis=0)
+    E, dedn, dedsigma = energy_and_partials(n, sigma, cell, kernel, flavour)
+    div = sum(spectral_derivative(2.0 * dedsigma * g[i], cell, i) for i in range(3))
+    return E, dedn - div, dedn, dedsigma
