@@ -1,0 +1,128 @@
+/* vdwxc_gpu.h - C ABI of the MI355X (gfx950) vdW-DF nonlocal-correlation library.
+ *
+ * The library evaluates the nonlocal correlation energy of the vdW-DF family,
+ *     E_c^nl = 1/2 \iint n(r) phi(q0(r), q0(r'), |r - r'|) n(r') dr dr'        (paper eq. 2)
+ * in the Roman-Perez--Soler spline/FFT form (paper Sec. 2), with the five steps of the paper's
+ * Sec. 3 procedure: theta_a(r) = n p_a(q0) on an N_alpha-point q-mesh, forward 3D FFTs, the
+ * per-k contraction F_a(k) = sum_b phi_ab(|k|) theta_b(k) against a tabulated kernel that is
+ * linearly interpolated in k (with the energy, eq. enlk), inverse 3D FFTs, and the partial
+ * derivatives dE/dn, dE/dsigma (paper eqs. dedn, dedsigma); q0 follows the paper's appendix.
+ * Everything runs on one GPU in hand-written HIP kernels.
+ *
+ * Conventions shared by every call:
+ *  - Units: Hartree atomic units (bohr, electrons/bohr^3, Hartree).
+ *  - Grids: N1 x N2 x N3 points of a periodic cell, stored row-major [N1][N2][N3] (N3 fastest),
+ *    point (i,j,k) at r = (i/N1) a1 + (j/N2) a2 + (k/N3) a3.  Each N_i must be >= 1 and a product
+ *    of the primes 2, 3, 5, 7.  Limits: N3 <= 8192, N2 <= 8192, N1 <= 512 (FP64) / 1024
+ *    (FP32_MIXED).
+ *  - cell[9]: the lattice vectors a1, a2, a3 as rows, bohr; det(cell) must be > 0.
+ *  - Arrays: every array argument of a calculate call is a DEVICE pointer to float64 data owned
+ *    by the caller (e.g. a torch tensor); the library never frees or retains it after the call
+ *    returns, and never writes inputs.  Outputs are overwritten, not accumulated.
+ *  - Streams: all device work of a handle is enqueued on its HIP stream (hipStream_t passed as
+ *    void*; NULL = the default stream).  One handle must not be used by two host threads at once,
+ *    and calls on one handle are ordered by its stream.  Different handles are independent.
+ *  - Errors: every call returns a vdwxc_status; nothing throws across the ABI.  On error the
+ *    outputs are unspecified and vdwxc_last_error() holds a message.
+ */
+#ifndef VDWXC_GPU_H
+#define VDWXC_GPU_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vdwxc_ctx* vdwxc_handle; /* opaque: plans, tables, workspace, stream */
+
+typedef enum {
+  VDWXC_OK = 0,
+  VDWXC_EINVAL = 1,  /* bad argument: grid, cell, NULL pointer, unsupported size, NaN input */
+  VDWXC_ENOMEM = 2,  /* device or pinned-host allocation failed */
+  VDWXC_EDEVICE = 3, /* a HIP runtime call failed */
+  VDWXC_ETABLE = 4,  /* malformed kernel table (file or arrays) */
+  VDWXC_ESTATE = 5   /* handle is NULL or already finalized */
+} vdwxc_status;
+
+/* Functional flavour: the gradient coefficient Z_ab of q0 (paper appendix). */
+typedef enum { VDWXC_DF1 = 1 /* Z_ab = -0.8491 */, VDWXC_DF2 = 2 /* Z_ab = -1.887 */ } vdwxc_flavour;
+
+/* Arithmetic of the FFTs and the contraction.  FP64: everything in double precision (the
+ * paper's choice, Sec. 6).  FP32_MIXED: q0, splines and the spectral gradient in FP64, theta,
+ * FFTs, the kernel table and the contraction in FP32, energy and derivative sums in FP64. */
+typedef enum { VDWXC_FP64 = 0, VDWXC_FP32_MIXED = 1 } vdwxc_precision;
+
+/* Create a handle for one grid and cell (paper Sec. 6, steps 1-3: vdwxc_new, set_unit_cell,
+ * init).  grid[3] = {N1, N2, N3}; cell[9] as above.  The kernel table is read from
+ * kernel_table_path, a binary file: bytes "VDWK", uint32 version (=1), uint32 M (q-mesh points,
+ * 4 <= M <= 20), uint32 nk (>= 2), float64 kmax, float64 qmesh[M] (strictly increasing, > 0),
+ * float64 table[nk][M][M] with table[j][a][b] = phi_ab(j*kmax/(nk-1)) (symmetric in a, b), all
+ * little endian.  The grid's largest |G| must be below kmax (else VDWXC_EINVAL).  hip_stream is
+ * the stream later calls enqueue on.  On success *out receives the handle; it owns device memory
+ * of vdwxc_workspace_bytes() plus the tables, until vdwxc_finalize. */
+vdwxc_status vdwxc_init(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
+                        vdwxc_precision precision, const char* kernel_table_path, void* hip_stream);
+
+/* As vdwxc_init, with the kernel table given as HOST arrays (copied; the caller keeps
+ * ownership): qmesh[nq], table[nk][nq][nq] as in the file format. */
+vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
+                              vdwxc_precision precision, int nq, const double* qmesh, int nk, double kmax,
+                              const double* table, void* hip_stream);
+
+/* The paper's evaluation (Sec. 3 steps 1-5, Sec. 6 step 4): from the density n and
+ * sigma = |grad n|^2 (device, [N1][N2][N3]) compute the energy E_c^nl (written to *energy_host,
+ * a host pointer) and the partial derivatives dedn = dE/dn|_sigma, dedsigma = dE/dsigma|_n per
+ * grid point (device outputs, eqs. dedn and dedsigma; the derivative of E with respect to the
+ * value n_j at one point is dedn_j * Omega/N).  Points with n < 1e-30 are vacuum: their dedn and
+ * dedsigma are 0.  A NaN in n or sigma gives VDWXC_EINVAL.  Synchronises the handle's stream. */
+vdwxc_status vdwxc_calculate(vdwxc_handle h, const double* n, const double* sigma, double* dedn,
+                             double* dedsigma, double* energy_host);
+
+/* The potential v = dE/dn|_sigma - div(2 dE/dsigma grad n), the functional derivative delta E/delta n
+ * of paper Sec. 2 with sigma = |grad n|^2.  grad_n (device, [3][N1][N2][N3], Cartesian
+ * components) is the caller's gradient of n; NULL means the library takes the spectral gradient
+ * of n itself (then E is a function of n alone and dE/dn_j = v_j * Omega/N exactly).  The
+ * divergence is spectral; frequencies on a Nyquist index are dropped in both derivatives.
+ * Writes v (device, [N1][N2][N3]) and *energy_host (host).  Synchronises the handle's stream. */
+vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const double* grad_n, double* v,
+                                       double* energy_host);
+
+/* As vdwxc_calculate_potential but fully asynchronous on the handle's stream: the energy is
+ * written to energy_dev (a device double) when the stream reaches it, NaN if the input held a
+ * NaN.  The caller must keep n, grad_n, v and energy_dev alive until the stream has passed. */
+vdwxc_status vdwxc_calculate_potential_async(vdwxc_handle h, const double* n, const double* grad_n, double* v,
+                                             double* energy_dev);
+
+/* As vdwxc_calculate but asynchronous: the energy goes to the device double energy_dev. */
+vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double* sigma, double* dedn,
+                                   double* dedsigma, double* energy_dev);
+
+/* Device memory a handle for this grid allocates for its work buffers (excluding the kernel
+ * table and plans), for admission control; 0 if the grid is invalid.  Host-only. */
+size_t vdwxc_workspace_bytes(const int grid[3], vdwxc_precision precision, int nq);
+
+/* Change the stream later calls enqueue on. */
+vdwxc_status vdwxc_set_stream(vdwxc_handle h, void* hip_stream);
+
+/* Print the handle's state (grid, cell, precision, table, memory) to stdout (paper Sec. 6). */
+vdwxc_status vdwxc_print(vdwxc_handle h);
+
+/* Release all memory of *h and set *h = NULL (paper Sec. 6, step 5).  Waits for the stream. */
+vdwxc_status vdwxc_finalize(vdwxc_handle* h);
+
+/* Static description of a status code. */
+const char* vdwxc_strerror(vdwxc_status s);
+
+/* Message of the last failing call on h; with h == NULL, of the last failing vdwxc_init* call
+ * of this thread.  Valid until the next call on the same handle / thread. */
+const char* vdwxc_last_error(vdwxc_handle h);
+
+/* Library version string. */
+const char* vdwxc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VDWXC_GPU_H */

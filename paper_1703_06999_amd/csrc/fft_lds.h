@@ -1,0 +1,221 @@
+// Batched 1D FFTs of lines held in LDS, for gfx950 (64-wide wavefronts).
+//
+// A workgroup owns `nlines` lines of length n, stored in LDS at buf[l*lstride + i].  Each radix-R
+// stage is a Stockham autosort step: butterfly i (0 <= i < n/R) of a line reads the R elements
+// i + r*n/R, applies twiddles exp(-+2 pi i r k/(pR)) with k = i mod p (p = product of the radices
+// already done), runs an R-point DFT and writes element (i - k)*R + k + r*p.  Output is in natural
+// order after the last stage.  A stage is two-phase: every thread first pulls its butterflies
+// into registers, the workgroup synchronises, and then all threads write back in place, so one
+// LDS buffer suffices.  The transforms are unnormalised; DIR = -1 is the forward direction
+// exp(-2 pi i jm/n), DIR = +1 the inverse.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace vdwxc {
+
+constexpr int kMaxStages = 16;
+
+// Radix schedule of one transform length: radices 8, 4, 2, 3, 5, 7.
+struct AxisPlan {
+  int n;
+  int nst;
+  int radix[kMaxStages];
+};
+
+template <typename T> struct Cx;
+template <> struct Cx<float> { using type = float2; };
+template <> struct Cx<double> { using type = double2; };
+
+template <typename T2> __device__ __forceinline__ T2 cadd(T2 a, T2 b) { return T2{a.x + b.x, a.y + b.y}; }
+template <typename T2> __device__ __forceinline__ T2 csub(T2 a, T2 b) { return T2{a.x - b.x, a.y - b.y}; }
+template <typename T2> __device__ __forceinline__ T2 cmul(T2 a, T2 b) {
+  return T2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by -i (DIR=-1) or +i (DIR=+1)
+template <int DIR, typename T2> __device__ __forceinline__ T2 rot90(T2 a) {
+  return DIR < 0 ? T2{a.y, -a.x} : T2{-a.y, a.x};
+}
+
+// ---- small DFTs, in place on v[0..R-1] -------------------------------------------------------
+
+template <int R, int DIR, typename T2> struct SmallDft;
+
+template <int DIR, typename T2> struct SmallDft<2, DIR, T2> {
+  __device__ __forceinline__ static void run(T2* v) {
+    T2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int DIR, typename T2> struct SmallDft<4, DIR, T2> {
+  __device__ __forceinline__ static void run(T2* v) {
+    T2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    T2 t2 = cadd(v[1], v[3]), t3 = rot90<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <int DIR, typename T2> struct SmallDft<8, DIR, T2> {
+  __device__ __forceinline__ static void run(T2* v) {
+    using T = decltype(v[0].x);
+    const T s = T(0.7071067811865475244008444);
+    T2 e[4] = {v[0], v[2], v[4], v[6]};
+    T2 o[4] = {v[1], v[3], v[5], v[7]};
+    SmallDft<4, DIR, T2>::run(e);
+    SmallDft<4, DIR, T2>::run(o);
+    // o[k] *= exp(DIR * 2 pi i k / 8)
+    o[1] = T2{s * (o[1].x - DIR * o[1].y), s * (o[1].y + DIR * o[1].x)};
+    o[2] = rot90<DIR>(o[2]);
+    o[3] = T2{-s * (o[3].x + DIR * o[3].y), s * (DIR * o[3].x - o[3].y)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + 4] = csub(e[k], o[k]);
+    }
+  }
+};
+
+template <int DIR, typename T2> struct SmallDft<3, DIR, T2> {
+  __device__ __forceinline__ static void run(T2* v) {
+    using T = decltype(v[0].x);
+    const T h = T(0.8660254037844386467637232);
+    T2 t = cadd(v[1], v[2]);
+    T2 s = csub(v[1], v[2]);
+    T2 m = T2{v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
+    T2 r = rot90<DIR>(T2{h * s.x, h * s.y});
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+};
+
+// odd radices 5 and 7: pairs (j, R-j) combine into cosine and sine sums
+template <int R> struct OddTrig;
+template <> struct OddTrig<5> {
+  __device__ __forceinline__ static double c(int t) {
+    return t == 1 || t == 4 ? 0.3090169943749474241022934 : -0.8090169943749474241022934;
+  }
+  __device__ __forceinline__ static double s(int t) {
+    return t == 1 ? 0.9510565162951535721164393 : t == 2 ? 0.5877852522924731291687060
+         : t == 3 ? -0.5877852522924731291687060 : -0.9510565162951535721164393;
+  }
+};
+template <> struct OddTrig<7> {
+  __device__ __forceinline__ static double c(int t) {
+    return (t == 1 || t == 6) ? 0.6234898018587335305250049
+         : (t == 2 || t == 5) ? -0.2225209339563144042889026 : -0.9009688679024191262361023;
+  }
+  __device__ __forceinline__ static double s(int t) {
+    return t == 1 ? 0.7818314824680298087084445 : t == 2 ? 0.9749279121818236070181317
+         : t == 3 ? 0.4338837391175581204757683 : t == 4 ? -0.4338837391175581204757683
+         : t == 5 ? -0.9749279121818236070181317 : -0.7818314824680298087084445;
+  }
+};
+
+template <int R, int DIR, typename T2> struct OddDft {
+  __device__ __forceinline__ static void run(T2* v) {
+    using T = decltype(v[0].x);
+    constexpr int H = (R - 1) / 2;
+    T2 A[H], B[H];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      A[j - 1] = cadd(v[j], v[R - j]);
+      B[j - 1] = csub(v[j], v[R - j]);
+    }
+    T2 x0 = v[0];
+    T2 sum = x0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) sum = cadd(sum, A[j]);
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      T2 cs = x0, sn = T2{T(0), T(0)};
+#pragma unroll
+      for (int j = 1; j <= H; ++j) {
+        const T c = T(OddTrig<R>::c((j * k) % R));
+        const T s = T(OddTrig<R>::s((j * k) % R));
+        cs.x += c * A[j - 1].x;
+        cs.y += c * A[j - 1].y;
+        sn.x += s * B[j - 1].x;
+        sn.y += s * B[j - 1].y;
+      }
+      // forward: X[k] = cs - i sn, X[R-k] = cs + i sn; inverse swaps the signs
+      T2 isn = rot90<DIR>(sn);
+      v[k] = cadd(cs, isn);
+      v[R - k] = csub(cs, isn);
+    }
+    v[0] = sum;
+  }
+};
+template <int DIR, typename T2> struct SmallDft<5, DIR, T2> : OddDft<5, DIR, T2> {};
+template <int DIR, typename T2> struct SmallDft<7, DIR, T2> : OddDft<7, DIR, T2> {};
+
+// ---- one Stockham stage on LDS lines ---------------------------------------------------------
+
+template <int R, int MAXB, int DIR, typename T2>
+__device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstride, int p,
+                                          const T2* __restrict__ tw, int tid, int nthr) {
+  const int nb = n / R;
+  const int total = nb * nlines;
+  const int twstep = n / (p * R);
+  T2 v[MAXB][R];
+  int dst[MAXB];
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    const int b = tid + c * nthr;
+    dst[c] = -1;
+    if (b < total) {
+      const int l = b / nb;
+      const int i = b - l * nb;
+      const int k = i % p;
+      const T2* src = buf + l * lstride + i;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[c][r] = src[r * nb];
+      if (p > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          T2 w = tw[r * k * twstep];
+          if (DIR > 0) w.y = -w.y;
+          v[c][r] = cmul(v[c][r], w);
+        }
+      }
+      SmallDft<R, DIR, T2>::run(v[c]);
+      dst[c] = l * lstride + (i - k) * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < MAXB; ++c) {
+    if (dst[c] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[dst[c] + r * p] = v[c][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Transform `nlines` LDS lines of length plan.n.  Requires nlines * n <= nthr * EPT.  The caller
+// must have synchronised after filling the lines; the lines are complete on return.
+template <int EPT, int DIR, typename T2>
+__device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
+                        const T2* __restrict__ tw, int tid, int nthr) {
+  const int n = plan.n;
+  int p = 1;
+  for (int s = 0; s < plan.nst; ++s) {
+    const int R = plan.radix[s];
+    switch (R) {
+      case 8: fft_stage<8, (EPT + 7) / 8, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
+      case 4: fft_stage<4, (EPT + 3) / 4, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
+      case 2: fft_stage<2, (EPT + 1) / 2, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
+      case 3: fft_stage<3, (EPT + 2) / 3, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
+      case 5: fft_stage<5, (EPT + 4) / 5, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
+      default: fft_stage<7, (EPT + 6) / 7, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
+    }
+    p *= R;
+  }
+}
+
+}  // namespace vdwxc

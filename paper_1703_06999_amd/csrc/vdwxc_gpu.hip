@@ -1,0 +1,682 @@
+// Host runtime and C ABI of the vdW-DF nonlocal-correlation library (see include/vdwxc_gpu.h).
+//
+// A handle holds: the grid and cell, per-axis FFT plans and twiddle tables, the q-mesh with the
+// second-derivative matrix of its natural helper splines, the kernel table (FP64 or FP32), two
+// complex work buffers A and B, the dE/dsigma and gradient buffers of the potential entry, the
+// per-column energy partials and a NaN flag.  A calculate call only enqueues kernels on the
+// handle's stream; the synchronous entry points then copy back one small result.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/vdwxc_gpu.h"
+#include "kernels.h"
+
+using namespace vdwxc;
+
+namespace {
+
+constexpr int kPPT = 8;        // grid points per thread in the z passes
+constexpr int kEPT = 8;        // FFT elements per thread in the z and y passes
+constexpr int kEPTX = 8;       // FFT elements per thread in the x passes
+constexpr int kMaxThreads = 512;
+constexpr int kLineTile = 16;  // lines per block in the z and y passes
+constexpr size_t kMaxLds = 160 * 1024;
+
+thread_local std::string g_init_error;
+
+struct Launch {
+  int tile = 1, nthr = 64, lstride = 1;
+  size_t lds = 0;
+};
+
+}  // namespace
+
+struct vdwxc_ctx {
+  int n1 = 0, n2 = 0, n3 = 0, h3 = 0;
+  double cell[9] = {0};
+  double omega = 0.0;
+  vdwxc_flavour flavour = VDWXC_DF1;
+  vdwxc_precision precision = VDWXC_FP64;
+  int M = 0, nk = 0;
+  double kmax = 0.0;
+  std::vector<double> qmesh;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Geometry geo{};
+  AxisPlan plan[3]{};
+  Launch zl64, zl32, yl64, yl32, xl64, xl32, xs64, xs32;
+  // device memory
+  double* d_q = nullptr;
+  double* d_mm = nullptr;
+  double* d_table64 = nullptr;
+  float* d_table32 = nullptr;
+  double2* d_tw64[3] = {nullptr, nullptr, nullptr};
+  float2* d_tw32[3] = {nullptr, nullptr, nullptr};
+  void* d_A = nullptr;
+  void* d_B = nullptr;
+  size_t buf_bytes = 0;
+  double* d_S = nullptr;       // dE/dsigma of the potential entry
+  double* d_G = nullptr;       // spectral gradient [3][N]
+  double* d_partials = nullptr;
+  double* d_energy = nullptr;  // energy of the synchronous entries
+  int* d_flag = nullptr;
+  double* h_energy = nullptr;  // pinned
+  int* h_flag = nullptr;       // pinned
+  std::string last_error;
+};
+
+namespace {
+
+vdwxc_status fail(vdwxc_ctx* h, vdwxc_status s, const std::string& msg) {
+  if (h) h->last_error = msg; else g_init_error = msg;
+  return s;
+}
+
+#define HIP_TRY(h, expr)                                                                      \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail((h), e_ == hipErrorOutOfMemory ? VDWXC_ENOMEM : VDWXC_EDEVICE,              \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                         \
+  } while (0)
+
+bool factor_axis(int n, AxisPlan& p) {
+  p.n = n;
+  p.nst = 0;
+  int m = n;
+  while (m % 8 == 0 && p.nst < kMaxStages) { p.radix[p.nst++] = 8; m /= 8; }
+  if (m % 4 == 0) { p.radix[p.nst++] = 4; m /= 4; }
+  if (m % 2 == 0) { p.radix[p.nst++] = 2; m /= 2; }
+  for (int r : {3, 5, 7}) {
+    while (m % r == 0) {
+      if (p.nst >= kMaxStages) return false;
+      p.radix[p.nst++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
+double det3(const double* c) {
+  return c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) + c[2] * (c[3] * c[7] - c[4] * c[6]);
+}
+
+// b_i with a_i . b_j = 2 pi delta_ij: rows of 2 pi (A^-1)^T
+void reciprocal(const double* a, double* b) {
+  const double d = det3(a);
+  const double inv[9] = {
+      (a[4] * a[8] - a[5] * a[7]) / d, (a[2] * a[7] - a[1] * a[8]) / d, (a[1] * a[5] - a[2] * a[4]) / d,
+      (a[5] * a[6] - a[3] * a[8]) / d, (a[0] * a[8] - a[2] * a[6]) / d, (a[2] * a[3] - a[0] * a[5]) / d,
+      (a[3] * a[7] - a[4] * a[6]) / d, (a[1] * a[6] - a[0] * a[7]) / d, (a[0] * a[4] - a[1] * a[3]) / d};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) b[3 * i + j] = 2.0 * M_PI * inv[3 * j + i];
+}
+
+// largest |G|^2 of the grid (Nyquist components in quadrature): a convex form on every face of
+// the index box, so the extreme signed frequencies and the Nyquist index are the candidates
+double max_gnorm2(const int n[3], const double* b) {
+  std::vector<int> cand[3];
+  for (int i = 0; i < 3; ++i) {
+    const int lo = (n[i] - 1) / 2;
+    cand[i] = {-lo, lo};
+    if (n[i] % 2 == 0) cand[i].push_back(n[i] / 2);
+  }
+  double best = 0.0;
+  for (int fx : cand[0])
+    for (int fy : cand[1])
+      for (int fz : cand[2]) {
+        const int f[3] = {fx, fy, fz};
+        double reg[3] = {0, 0, 0}, nyq[3] = {0, 0, 0};
+        for (int i = 0; i < 3; ++i) {
+          const bool isn = (n[i] % 2 == 0) && f[i] == n[i] / 2;
+          for (int c = 0; c < 3; ++c) (isn ? nyq : reg)[c] += f[i] * b[3 * i + c];
+        }
+        const double g2 = reg[0] * reg[0] + reg[1] * reg[1] + reg[2] * reg[2] + nyq[0] * nyq[0] +
+                          nyq[1] * nyq[1] + nyq[2] * nyq[2];
+        best = std::max(best, g2);
+      }
+  return best;
+}
+
+// second derivatives mm[a][b] of the natural cubic splines through p_a(q_b) = delta_ab
+void natural_spline_moments(const std::vector<double>& q, std::vector<double>& mm) {
+  const int M = int(q.size());
+  mm.assign(size_t(M) * M, 0.0);
+  std::vector<double> h(M - 1), diag(M), rhs(M), sup(M);
+  for (int i = 0; i + 1 < M; ++i) h[i] = q[i + 1] - q[i];
+  for (int a = 0; a < M; ++a) {
+    // interior equations i = 1..M-2: h_{i-1} m_{i-1} + 2(h_{i-1}+h_i) m_i + h_i m_{i+1} = r_i
+    std::vector<double> y(M, 0.0);
+    y[a] = 1.0;
+    const int K = M - 2;
+    if (K <= 0) continue;
+    std::vector<double> cprime(K), dprime(K);
+    for (int r = 0; r < K; ++r) {
+      const int i = r + 1;
+      const double lower = h[i - 1], diagv = 2.0 * (h[i - 1] + h[i]), upper = h[i];
+      const double rr = 6.0 * ((y[i + 1] - y[i]) / h[i] - (y[i] - y[i - 1]) / h[i - 1]);
+      if (r == 0) {
+        cprime[r] = upper / diagv;
+        dprime[r] = rr / diagv;
+      } else {
+        const double den = diagv - lower * cprime[r - 1];
+        cprime[r] = upper / den;
+        dprime[r] = (rr - lower * dprime[r - 1]) / den;
+      }
+    }
+    std::vector<double> m(M, 0.0);
+    for (int r = K - 1; r >= 0; --r) m[r + 1] = dprime[r] - (r + 1 < K ? cprime[r] * m[r + 2] : 0.0);
+    for (int b = 0; b < M; ++b) mm[size_t(a) * M + b] = m[b];
+  }
+}
+
+template <typename T2, typename T>
+std::vector<T2> twiddles(int n) {
+  std::vector<T2> tw(std::max(n, 1));
+  for (int t = 0; t < n; ++t) {
+    const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)t / (long double)n;
+    tw[t].x = T(cosl(ang));
+    tw[t].y = T(-sinl(ang));
+  }
+  return tw;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// block size with >= `items / ept` threads, a multiple of 64, at most kMaxThreads
+int threads_for(long items, int ept) {
+  const long t = (items + ept - 1) / ept;
+  return int(std::min<long>(kMaxThreads, std::max<long>(64, round_up(int(std::min<long>(t, 1 << 20)), 64))));
+}
+
+bool line_launch(int nlines_max, int n, int other, size_t cplx_bytes, Launch& L) {
+  // TILE lines of length n in one block (TILE <= min(16, other)), padded stride n + 1
+  int tile = std::min(kLineTile, std::max(1, other));
+  while (tile > 1 && long(tile) * n > long(kMaxThreads) * kEPT) tile /= 2;
+  if (long(tile) * n > long(kMaxThreads) * kEPT) return false;
+  (void)nlines_max;
+  L.tile = tile;
+  L.nthr = threads_for(long(tile) * n, kEPT);
+  L.lstride = n + 1;
+  L.lds = size_t(tile) * (n + 1) * cplx_bytes;
+  return L.lds + 4096 <= kMaxLds;
+}
+
+bool xline_launch(int nlines, int n, size_t cplx_bytes, Launch& L) {
+  // all field lines of one column in LDS, transformed in groups of nthr * EPT / n lines
+  if (n > kMaxThreads * kEPTX) return false;
+  L.tile = nlines;
+  L.nthr = threads_for(long(nlines) * n, kEPTX);
+  L.lstride = n;
+  L.lds = std::max<size_t>(size_t(nlines) * n * cplx_bytes, 16 * sizeof(double));
+  return L.lds <= kMaxLds;
+}
+
+size_t complex_buffer_bytes(int n1, int n2, int n3, vdwxc_precision p, int M) {
+  const size_t nk = size_t(n1) * n2 * (n3 / 2 + 1);
+  const size_t fields = (p == VDWXC_FP64) ? std::max(M, 3) * 16 : std::max<size_t>(M * 8, 3 * 16);
+  return nk * fields;
+}
+
+template <typename F>
+void set_lds_limit(F* kernel, size_t bytes) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int(bytes));
+}
+
+vdwxc_status validate_common(const int grid[3], const double cell[9]) {
+  if (!grid || !cell) return fail(nullptr, VDWXC_EINVAL, "grid and cell must not be NULL");
+  for (int i = 0; i < 3; ++i)
+    if (grid[i] < 1) return fail(nullptr, VDWXC_EINVAL, "grid sizes must be >= 1");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(cell[i])) return fail(nullptr, VDWXC_EINVAL, "cell contains NaN/inf");
+  if (!(det3(cell) > 0.0)) return fail(nullptr, VDWXC_EINVAL, "cell must have positive volume (right-handed)");
+  return VDWXC_OK;
+}
+
+void release(vdwxc_ctx* h) {
+  if (!h) return;
+  auto f = [](void* p) { if (p) (void)hipFree(p); };
+  f(h->d_q); f(h->d_mm); f(h->d_table64); f(h->d_table32);
+  for (int i = 0; i < 3; ++i) { f(h->d_tw64[i]); f(h->d_tw32[i]); }
+  f(h->d_A); f(h->d_B); f(h->d_S); f(h->d_G); f(h->d_partials); f(h->d_energy); f(h->d_flag);
+  if (h->h_energy) (void)hipHostFree(h->h_energy);
+  if (h->h_flag) (void)hipHostFree(h->h_flag);
+  delete h;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const T* src, size_t count) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+struct Prec;
+template <> struct Prec<double> {
+  static const Launch& z(const vdwxc_ctx* h) { return h->zl64; }
+  static const Launch& y(const vdwxc_ctx* h) { return h->yl64; }
+  static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
+  static const Launch& xs(const vdwxc_ctx* h) { return h->xs64; }
+  static const double2* tw(const vdwxc_ctx* h, int a) { return h->d_tw64[a]; }
+  static const double* table(const vdwxc_ctx* h) { return h->d_table64; }
+};
+template <> struct Prec<float> {
+  static const Launch& z(const vdwxc_ctx* h) { return h->zl32; }
+  static const Launch& y(const vdwxc_ctx* h) { return h->yl32; }
+  static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
+  static const Launch& xs(const vdwxc_ctx* h) { return h->xs32; }
+  static const float2* tw(const vdwxc_ctx* h, int a) { return h->d_tw32[a]; }
+  static const float* table(const vdwxc_ctx* h) { return h->d_table32; }
+};
+
+template <typename T>
+void enqueue_ypass(vdwxc_ctx* h, int nf, int dir) {
+  using T2 = typename Cx<T>::type;
+  const Launch& L = Prec<T>::y(h);
+  dim3 grid((h->n1 + L.tile - 1) / L.tile, h->h3, nf);
+  T2* A = static_cast<T2*>(h->d_A);
+  T2* B = static_cast<T2*>(h->d_B);
+  if (dir < 0)
+    hipLaunchKernelGGL((k_ypass<T, kEPT, -1>), grid, dim3(L.nthr), L.lds, h->stream, A, B, Prec<T>::tw(h, 1),
+                       h->geo, h->plan[1], L.tile, L.lstride);
+  else
+    hipLaunchKernelGGL((k_ypass<T, kEPT, +1>), grid, dim3(L.nthr), L.lds, h->stream, B, A, Prec<T>::tw(h, 1),
+                       h->geo, h->plan[1], L.tile, L.lstride);
+}
+
+// forward FFT of nf real FP64 fields (MODE 0) or of 2 S g_c (MODE 1), through z, y, x; then the
+// x-pass spectral operator (1 -> 3 gradient or 3 -> 1 divergence), inverse x, y, and z into out
+template <typename T>
+void enqueue_spectral(vdwxc_ctx* h, int mode, const double* src, const double* aux, int nin, int nout,
+                      double* out) {
+  using T2 = typename Cx<T>::type;
+  const Launch& Lz = Prec<T>::z(h);
+  const Launch& Lx = Prec<T>::xs(h);
+  T2* A = static_cast<T2*>(h->d_A);
+  T2* B = static_cast<T2*>(h->d_B);
+  Geometry g = h->geo;
+  g.M = nin;
+  dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_real_zfwd<T, kEPT, 0>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, src, aux, nin, A,
+                       Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
+  else
+    hipLaunchKernelGGL((k_real_zfwd<T, kEPT, 1>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, src, aux, nin, A,
+                       Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
+  enqueue_ypass<T>(h, nin, -1);
+  dim3 xgrid(h->n2, h->h3);
+  if (nin == 1)
+    hipLaunchKernelGGL((k_xspectral<T, kEPTX, 1, 3>), xgrid, dim3(Lx.nthr), Lx.lds, h->stream, B,
+                       Prec<T>::tw(h, 0), g, h->plan[0]);
+  else
+    hipLaunchKernelGGL((k_xspectral<T, kEPTX, 3, 1>), xgrid, dim3(Lx.nthr), Lx.lds, h->stream, B,
+                       Prec<T>::tw(h, 0), g, h->plan[0]);
+  enqueue_ypass<T>(h, nout, +1);
+  if (nout == 3)
+    hipLaunchKernelGGL((k_real_zinv<T, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, nout, out,
+                       Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
+  else
+    hipLaunchKernelGGL((k_real_zinv<T, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, nout, out,
+                       Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
+}
+
+// the five steps: theta + z FFT, y FFT, x FFT + contraction + inverse x, inverse y, inverse z +
+// derivatives; then the energy sum
+template <typename T>
+void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_from_grad, double* dedn,
+                  double* dedsig, double* energy) {
+  using T2 = typename Cx<T>::type;
+  const Launch& Lz = Prec<T>::z(h);
+  const Launch& Lx = Prec<T>::x(h);
+  T2* A = static_cast<T2*>(h->d_A);
+  T2* B = static_cast<T2*>(h->d_B);
+  dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
+  if (sig_from_grad)
+    hipLaunchKernelGGL((k_theta_zfwd<T, kPPT, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, n, sig, A,
+                       h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
+  else
+    hipLaunchKernelGGL((k_theta_zfwd<T, kPPT, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, n, sig, A,
+                       h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
+  enqueue_ypass<T>(h, h->M, -1);
+  hipLaunchKernelGGL((k_xcontract<T, kEPTX>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
+                     Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+  enqueue_ypass<T>(h, h->M, +1);
+  if (sig_from_grad)
+    hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, n,
+                       sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile,
+                       Lz.lstride);
+  else
+    hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, n,
+                       sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile,
+                       Lz.lstride);
+  const double N = double(h->n1) * h->n2 * h->n3;
+  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(512), 0, h->stream, h->d_partials, h->n2 * h->h3,
+                     h->omega / (2.0 * N * N), h->d_flag, energy);
+}
+
+vdwxc_status check_handle(vdwxc_ctx* h) {
+  if (!h) return VDWXC_ESTATE;
+  return VDWXC_OK;
+}
+
+vdwxc_status finish_launch(vdwxc_ctx* h) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(h, VDWXC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return VDWXC_OK;
+}
+
+vdwxc_status run_partials(vdwxc_ctx* h, const double* n, const double* sigma, double* dedn, double* dedsig,
+                          double* energy_dev) {
+  HIP_TRY(h, hipSetDevice(h->device));
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, h->stream, h->d_flag);
+  if (h->precision == VDWXC_FP64)
+    enqueue_main<double>(h, n, sigma, false, dedn, dedsig, energy_dev);
+  else
+    enqueue_main<float>(h, n, sigma, false, dedn, dedsig, energy_dev);
+  return finish_launch(h);
+}
+
+vdwxc_status run_potential(vdwxc_ctx* h, const double* n, const double* grad, double* v, double* energy_dev) {
+  HIP_TRY(h, hipSetDevice(h->device));
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, h->stream, h->d_flag);
+  const double* g = grad;
+  if (!g) {
+    // the gradient feeds q0, so it is taken in FP64 in both precisions
+    enqueue_spectral<double>(h, 0, n, nullptr, 1, 3, h->d_G);
+    g = h->d_G;
+  }
+  if (h->precision == VDWXC_FP64) {
+    enqueue_main<double>(h, n, g, true, v, h->d_S, energy_dev);
+    enqueue_spectral<double>(h, 1, h->d_S, g, 3, 1, v);
+  } else {
+    enqueue_main<float>(h, n, g, true, v, h->d_S, energy_dev);
+    enqueue_spectral<float>(h, 1, h->d_S, g, 3, 1, v);
+  }
+  return finish_launch(h);
+}
+
+vdwxc_status read_energy(vdwxc_ctx* h, double* energy_host) {
+  HIP_TRY(h, hipMemcpyAsync(h->h_energy, h->d_energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->h_flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (*h->h_flag) return fail(h, VDWXC_EINVAL, "density or gradient input contains NaN");
+  *energy_host = *h->h_energy;
+  return VDWXC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* vdwxc_version(void) { return "vdwxc-gpu 0.1 (gfx950)"; }
+
+const char* vdwxc_strerror(vdwxc_status s) {
+  switch (s) {
+    case VDWXC_OK: return "success";
+    case VDWXC_EINVAL: return "invalid argument";
+    case VDWXC_ENOMEM: return "out of memory";
+    case VDWXC_EDEVICE: return "HIP device error";
+    case VDWXC_ETABLE: return "malformed kernel table";
+    case VDWXC_ESTATE: return "invalid or finalized handle";
+  }
+  return "unknown status";
+}
+
+const char* vdwxc_last_error(vdwxc_handle h) { return h ? h->last_error.c_str() : g_init_error.c_str(); }
+
+size_t vdwxc_workspace_bytes(const int grid[3], vdwxc_precision precision, int nq) {
+  if (!grid || grid[0] < 1 || grid[1] < 1 || grid[2] < 1 || nq < 1) return 0;
+  const size_t N = size_t(grid[0]) * grid[1] * grid[2];
+  const size_t cplx = complex_buffer_bytes(grid[0], grid[1], grid[2], precision, nq);
+  return 2 * cplx + 4 * N * sizeof(double) + size_t(grid[1]) * (grid[2] / 2 + 1) * sizeof(double) + 64;
+}
+
+vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
+                              vdwxc_precision precision, int nq, const double* qmesh, int nk, double kmax,
+                              const double* table, void* hip_stream) {
+  if (!out) return fail(nullptr, VDWXC_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  vdwxc_status st = validate_common(grid, cell);
+  if (st != VDWXC_OK) return st;
+  if (flavour != VDWXC_DF1 && flavour != VDWXC_DF2) return fail(nullptr, VDWXC_EINVAL, "unknown flavour");
+  if (precision != VDWXC_FP64 && precision != VDWXC_FP32_MIXED)
+    return fail(nullptr, VDWXC_EINVAL, "unknown precision");
+  if (!qmesh || !table) return fail(nullptr, VDWXC_ETABLE, "kernel table arrays must not be NULL");
+  if (nq < 4 || nq > kMaxQ) return fail(nullptr, VDWXC_ETABLE, "q-mesh size must be in [4, 20]");
+  if (nk < 2 || !(kmax > 0.0) || !std::isfinite(kmax)) return fail(nullptr, VDWXC_ETABLE, "bad kernel k-grid");
+  for (int i = 0; i < nq; ++i) {
+    if (!std::isfinite(qmesh[i]) || !(qmesh[i] > 0.0) || (i > 0 && !(qmesh[i] > qmesh[i - 1])))
+      return fail(nullptr, VDWXC_ETABLE, "q-mesh must be positive and strictly increasing");
+  }
+  const size_t tsz = size_t(nk) * nq * nq;
+  for (size_t i = 0; i < tsz; ++i)
+    if (!std::isfinite(table[i])) return fail(nullptr, VDWXC_ETABLE, "kernel table contains NaN/inf");
+  for (int j = 0; j < nk; ++j)
+    for (int a = 0; a < nq; ++a)
+      for (int b = 0; b < a; ++b) {
+        const double x = table[(size_t(j) * nq + a) * nq + b], y = table[(size_t(j) * nq + b) * nq + a];
+        if (std::fabs(x - y) > 1e-12 * std::max(std::fabs(x), std::fabs(y)))
+          return fail(nullptr, VDWXC_ETABLE, "kernel table must be symmetric in (a, b)");
+      }
+
+  vdwxc_ctx* h = new (std::nothrow) vdwxc_ctx();
+  if (!h) return fail(nullptr, VDWXC_ENOMEM, "host allocation failed");
+  h->n1 = grid[0];
+  h->n2 = grid[1];
+  h->n3 = grid[2];
+  h->h3 = grid[2] / 2 + 1;
+  std::memcpy(h->cell, cell, sizeof(h->cell));
+  h->omega = det3(cell);
+  h->flavour = flavour;
+  h->precision = precision;
+  h->M = nq;
+  h->nk = nk;
+  h->kmax = kmax;
+  h->qmesh.assign(qmesh, qmesh + nq);
+  h->stream = static_cast<hipStream_t>(hip_stream);
+
+  const int n[3] = {h->n1, h->n2, h->n3};
+  for (int a = 0; a < 3; ++a)
+    if (!factor_axis(n[a], h->plan[a])) {
+      release(h);
+      return fail(nullptr, VDWXC_EINVAL, "grid sizes must be products of 2, 3, 5 and 7");
+    }
+  Geometry& g = h->geo;
+  g.n1 = h->n1; g.n2 = h->n2; g.n3 = h->n3; g.h3 = h->h3; g.M = nq;
+  g.zab = flavour == VDWXC_DF1 ? -0.8491 : -1.887;
+  reciprocal(cell, g.bvec);
+  g.kmax = kmax;
+  g.nk = nk;
+  g.inv_dk = double(nk - 1) / kmax;
+  if (!(max_gnorm2(n, g.bvec) < kmax * kmax)) {
+    release(h);
+    return fail(nullptr, VDWXC_EINVAL, "grid reaches |G| >= kmax of the kernel table (grid too fine)");
+  }
+  bool ok = line_launch(0, h->n3, h->n2, 16, h->zl64) && line_launch(0, h->n3, h->n2, 8, h->zl32) &&
+            line_launch(0, h->n2, h->n1, 16, h->yl64) && line_launch(0, h->n2, h->n1, 8, h->yl32) &&
+            xline_launch(3, h->n1, 16, h->xs64) && xline_launch(3, h->n1, 8, h->xs32);
+  if (precision == VDWXC_FP64) ok = ok && xline_launch(nq, h->n1, 16, h->xl64);
+  else ok = ok && xline_launch(nq, h->n1, 8, h->xl32);
+  if (!ok) {
+    release(h);
+    return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
+  }
+
+  auto bail = [&](hipError_t e, const char* what) {
+    release(h);
+    return fail(nullptr, e == hipErrorOutOfMemory ? VDWXC_ENOMEM : VDWXC_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+  };
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) return bail(e, "hipGetDevice");
+  std::vector<double> mm;
+  natural_spline_moments(h->qmesh, mm);
+  if ((e = upload(&h->d_q, h->qmesh.data(), nq)) != hipSuccess) return bail(e, "q-mesh upload");
+  if ((e = upload(&h->d_mm, mm.data(), mm.size())) != hipSuccess) return bail(e, "spline upload");
+  if ((e = upload(&h->d_table64, table, tsz)) != hipSuccess) return bail(e, "table upload");
+  if (precision == VDWXC_FP32_MIXED) {
+    std::vector<float> t32(table, table + tsz);
+    if ((e = upload(&h->d_table32, t32.data(), tsz)) != hipSuccess) return bail(e, "table upload");
+  }
+  for (int a = 0; a < 3; ++a) {
+    auto t64 = twiddles<double2, double>(n[a]);
+    auto t32 = twiddles<float2, float>(n[a]);
+    if ((e = upload(&h->d_tw64[a], t64.data(), t64.size())) != hipSuccess) return bail(e, "twiddle upload");
+    if ((e = upload(&h->d_tw32[a], t32.data(), t32.size())) != hipSuccess) return bail(e, "twiddle upload");
+  }
+  const size_t N = size_t(h->n1) * h->n2 * h->n3;
+  h->buf_bytes = complex_buffer_bytes(h->n1, h->n2, h->n3, precision, nq);
+  if ((e = hipMalloc(&h->d_A, h->buf_bytes)) != hipSuccess) return bail(e, "work buffer A");
+  if ((e = hipMalloc(&h->d_B, h->buf_bytes)) != hipSuccess) return bail(e, "work buffer B");
+  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_S), N * sizeof(double))) != hipSuccess) return bail(e, "dE/dsigma buffer");
+  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_G), 3 * N * sizeof(double))) != hipSuccess) return bail(e, "gradient buffer");
+  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_partials), size_t(h->n2) * h->h3 * sizeof(double))) != hipSuccess)
+    return bail(e, "energy partials");
+  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_energy), sizeof(double))) != hipSuccess) return bail(e, "energy");
+  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_flag), sizeof(int))) != hipSuccess) return bail(e, "flag");
+  if ((e = hipHostMalloc(reinterpret_cast<void**>(&h->h_energy), sizeof(double), hipHostMallocDefault)) != hipSuccess)
+    return bail(e, "pinned energy");
+  if ((e = hipHostMalloc(reinterpret_cast<void**>(&h->h_flag), sizeof(int), hipHostMallocDefault)) != hipSuccess)
+    return bail(e, "pinned flag");
+
+  // dynamic LDS above the default limit
+  set_lds_limit(k_theta_zfwd<double, kPPT, kEPT, false>, h->zl64.lds);
+  set_lds_limit(k_theta_zfwd<double, kPPT, kEPT, true>, h->zl64.lds);
+  set_lds_limit(k_theta_zfwd<float, kPPT, kEPT, false>, h->zl32.lds);
+  set_lds_limit(k_theta_zfwd<float, kPPT, kEPT, true>, h->zl32.lds);
+  set_lds_limit(k_zinv_assemble<double, kPPT, kEPT, false>, h->zl64.lds);
+  set_lds_limit(k_zinv_assemble<double, kPPT, kEPT, true>, h->zl64.lds);
+  set_lds_limit(k_zinv_assemble<float, kPPT, kEPT, false>, h->zl32.lds);
+  set_lds_limit(k_zinv_assemble<float, kPPT, kEPT, true>, h->zl32.lds);
+  set_lds_limit(k_real_zfwd<double, kEPT, 0>, h->zl64.lds);
+  set_lds_limit(k_real_zfwd<double, kEPT, 1>, h->zl64.lds);
+  set_lds_limit(k_real_zfwd<float, kEPT, 1>, h->zl32.lds);
+  set_lds_limit(k_real_zinv<double, kEPT, false>, h->zl64.lds);
+  set_lds_limit(k_real_zinv<double, kEPT, true>, h->zl64.lds);
+  set_lds_limit(k_real_zinv<float, kEPT, true>, h->zl32.lds);
+  set_lds_limit(k_ypass<double, kEPT, -1>, h->yl64.lds);
+  set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
+  set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
+  set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32.lds);
+  if (precision == VDWXC_FP64) set_lds_limit(k_xcontract<double, kEPTX>, h->xl64.lds);
+  else set_lds_limit(k_xcontract<float, kEPTX>, h->xl32.lds);
+  set_lds_limit(k_xspectral<double, kEPTX, 1, 3>, h->xs64.lds);
+  set_lds_limit(k_xspectral<double, kEPTX, 3, 1>, h->xs64.lds);
+  set_lds_limit(k_xspectral<float, kEPTX, 3, 1>, h->xs32.lds);
+  (void)hipGetLastError();
+  *out = h;
+  return VDWXC_OK;
+}
+
+vdwxc_status vdwxc_init(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
+                        vdwxc_precision precision, const char* kernel_table_path, void* hip_stream) {
+  if (!out) return fail(nullptr, VDWXC_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (!kernel_table_path) return fail(nullptr, VDWXC_EINVAL, "kernel_table_path must not be NULL");
+  FILE* f = std::fopen(kernel_table_path, "rb");
+  if (!f) return fail(nullptr, VDWXC_ETABLE, std::string("cannot open kernel table ") + kernel_table_path);
+  char magic[4];
+  unsigned int hdr[3];
+  double kmax = 0.0;
+  bool ok = std::fread(magic, 1, 4, f) == 4 && std::memcmp(magic, "VDWK", 4) == 0 &&
+            std::fread(hdr, sizeof(unsigned int), 3, f) == 3 && hdr[0] == 1 && hdr[1] >= 4 &&
+            hdr[1] <= unsigned(kMaxQ) && hdr[2] >= 2 && hdr[2] < (1u << 24) && std::fread(&kmax, sizeof(double), 1, f) == 1;
+  std::vector<double> q, t;
+  if (ok) {
+    q.resize(hdr[1]);
+    t.resize(size_t(hdr[2]) * hdr[1] * hdr[1]);
+    ok = std::fread(q.data(), sizeof(double), q.size(), f) == q.size() &&
+         std::fread(t.data(), sizeof(double), t.size(), f) == t.size();
+  }
+  std::fclose(f);
+  if (!ok) return fail(nullptr, VDWXC_ETABLE, std::string("malformed kernel table file ") + kernel_table_path);
+  return vdwxc_init_table(out, grid, cell, flavour, precision, int(hdr[1]), q.data(), int(hdr[2]), kmax, t.data(),
+                          hip_stream);
+}
+
+vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double* sigma, double* dedn,
+                                   double* dedsigma, double* energy_dev) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (!n || !sigma || !dedn || !dedsigma || !energy_dev)
+    return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  return run_partials(h, n, sigma, dedn, dedsigma, energy_dev);
+}
+
+vdwxc_status vdwxc_calculate(vdwxc_handle h, const double* n, const double* sigma, double* dedn, double* dedsigma,
+                             double* energy_host) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (!n || !sigma || !dedn || !dedsigma || !energy_host)
+    return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  vdwxc_status st = run_partials(h, n, sigma, dedn, dedsigma, h->d_energy);
+  if (st != VDWXC_OK) return st;
+  return read_energy(h, energy_host);
+}
+
+vdwxc_status vdwxc_calculate_potential_async(vdwxc_handle h, const double* n, const double* grad_n, double* v,
+                                             double* energy_dev) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (!n || !v || !energy_dev) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  return run_potential(h, n, grad_n, v, energy_dev);
+}
+
+vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const double* grad_n, double* v,
+                                       double* energy_host) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (!n || !v || !energy_host) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  vdwxc_status st = run_potential(h, n, grad_n, v, h->d_energy);
+  if (st != VDWXC_OK) return st;
+  return read_energy(h, energy_host);
+}
+
+vdwxc_status vdwxc_set_stream(vdwxc_handle h, void* hip_stream) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return VDWXC_OK;
+}
+
+vdwxc_status vdwxc_print(vdwxc_handle h) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  std::printf("vdwxc_gpu handle: grid %d x %d x %d, cell [%g %g %g | %g %g %g | %g %g %g] bohr, volume %g bohr^3\n",
+              h->n1, h->n2, h->n3, h->cell[0], h->cell[1], h->cell[2], h->cell[3], h->cell[4], h->cell[5],
+              h->cell[6], h->cell[7], h->cell[8], h->omega);
+  std::printf("  flavour %s (Z_ab = %g), precision %s, q-mesh %d points [%g .. %g], kernel table %d x %d x %d to "
+              "k = %g\n",
+              h->flavour == VDWXC_DF1 ? "vdW-DF1" : "vdW-DF2", h->geo.zab,
+              h->precision == VDWXC_FP64 ? "FP64" : "FP32_MIXED", h->M, h->qmesh.front(), h->qmesh.back(), h->nk,
+              h->M, h->M, h->kmax);
+  std::printf("  work buffers 2 x %.3f MB, device %d\n", h->buf_bytes / 1e6, h->device);
+  std::fflush(stdout);
+  return VDWXC_OK;
+}
+
+vdwxc_status vdwxc_finalize(vdwxc_handle* hp) {
+  if (!hp || !*hp) return VDWXC_ESTATE;
+  vdwxc_ctx* h = *hp;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  release(h);
+  *hp = nullptr;
+  return VDWXC_OK;
+}
+
+}  // extern "C"
