@@ -118,6 +118,40 @@ const char* vdwxc_strerror(vdwxc_status s);
  * of this thread.  Valid until the next call on the same handle / thread. */
 const char* vdwxc_last_error(vdwxc_handle h);
 
+/* Kernel stages of one evaluation, for the timing calls below. */
+typedef enum {
+  VDWXC_STAGE_THETA_ZFWD = 0,   /* q0, splines, theta, forward z FFT (Sec. 3 steps 1-2) */
+  VDWXC_STAGE_Y_FWD = 1,        /* forward y FFT of the theta fields */
+  VDWXC_STAGE_X_CONTRACT = 2,   /* forward x FFT, k-space contraction + energy, inverse x FFT (steps 2-4) */
+  VDWXC_STAGE_Y_INV = 3,        /* inverse y FFT of the F fields */
+  VDWXC_STAGE_Z_ASSEMBLE = 4,   /* inverse z FFT and dE/dn, dE/dsigma (steps 4-5) */
+  VDWXC_STAGE_ENERGY = 5,       /* fixed-order energy sum */
+  VDWXC_STAGE_GRAD_Z = 6,       /* spectral gradient of n: z, y, x, y, z passes */
+  VDWXC_STAGE_GRAD_Y = 7,
+  VDWXC_STAGE_GRAD_X = 8,
+  VDWXC_STAGE_GRAD_YI = 9,
+  VDWXC_STAGE_GRAD_ZI = 10,
+  VDWXC_STAGE_DIV_Z = 11,       /* spectral divergence of 2 dE/dsigma grad n: z, y, x, y, z passes */
+  VDWXC_STAGE_DIV_Y = 12,
+  VDWXC_STAGE_DIV_X = 13,
+  VDWXC_STAGE_DIV_YI = 14,
+  VDWXC_STAGE_DIV_ZI = 15,
+  VDWXC_NUM_STAGES = 16
+} vdwxc_stage;
+
+/* Per-stage timing with HIP events recorded on the handle's stream around every kernel launch
+ * (off by default; recording adds no work to the kernels themselves).  enable != 0 turns it on
+ * and clears the accumulators. */
+vdwxc_status vdwxc_enable_timing(vdwxc_handle h, int enable);
+
+/* Synchronise the handle's stream and return, per stage, the summed kernel time in ms and the
+ * number of launches since the last enable/read (host arrays of VDWXC_NUM_STAGES entries); the
+ * accumulators are then cleared. */
+vdwxc_status vdwxc_read_timing(vdwxc_handle h, double* ms, long long* launches);
+
+/* Short name of a stage ("theta_zfwd", "x_contract", ...); "?" if out of range. */
+const char* vdwxc_stage_name(int stage);
+
 /* Library version string. */
 const char* vdwxc_version(void);
 

@@ -71,6 +71,14 @@ struct vdwxc_ctx {
   double* h_energy = nullptr;  // pinned
   int* h_flag = nullptr;       // pinned
   std::string last_error;
+  // stage timing
+  bool timing = false;
+  std::vector<hipEvent_t> free_events;
+  struct Pending { int stage; hipEvent_t start, stop; };
+  std::vector<Pending> pending;
+  double stage_ms[VDWXC_NUM_STAGES] = {0};
+  long long stage_count[VDWXC_NUM_STAGES] = {0};
+  hipEvent_t cur_start = nullptr;
 };
 
 namespace {
@@ -244,6 +252,8 @@ vdwxc_status validate_common(const int grid[3], const double cell[9]) {
 
 void release(vdwxc_ctx* h) {
   if (!h) return;
+  for (auto& p : h->pending) { (void)hipEventDestroy(p.start); (void)hipEventDestroy(p.stop); }
+  for (auto e : h->free_events) (void)hipEventDestroy(e);
   auto f = [](void* p) { if (p) (void)hipFree(p); };
   f(h->d_q); f(h->d_mm); f(h->d_table64); f(h->d_table32);
   for (int i = 0; i < 3; ++i) { f(h->d_tw64[i]); f(h->d_tw32[i]); }
@@ -286,19 +296,47 @@ template <> struct Prec<float> {
   static const float* table(const vdwxc_ctx* h) { return h->d_table32; }
 };
 
+hipEvent_t take_event(vdwxc_ctx* h) {
+  if (!h->free_events.empty()) {
+    hipEvent_t e = h->free_events.back();
+    h->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void stage_begin(vdwxc_ctx* h) {
+  if (!h->timing) return;
+  h->cur_start = take_event(h);
+  if (h->cur_start) (void)hipEventRecord(h->cur_start, h->stream);
+}
+
+void stage_end(vdwxc_ctx* h, int stage) {
+  if (!h->timing || !h->cur_start) return;
+  hipEvent_t stop = take_event(h);
+  if (!stop) return;
+  (void)hipEventRecord(stop, h->stream);
+  h->pending.push_back({stage, h->cur_start, stop});
+  h->cur_start = nullptr;
+}
+
 template <typename T>
-void enqueue_ypass(vdwxc_ctx* h, int nf, int dir) {
+void enqueue_ypass(vdwxc_ctx* h, int nf, int dir, int stage) {
   using T2 = typename Cx<T>::type;
   const Launch& L = Prec<T>::y(h);
   dim3 grid((h->n1 + L.tile - 1) / L.tile, h->h3, nf);
   T2* A = static_cast<T2*>(h->d_A);
   T2* B = static_cast<T2*>(h->d_B);
+  stage_begin(h);
   if (dir < 0)
     hipLaunchKernelGGL((k_ypass<T, kEPT, -1>), grid, dim3(L.nthr), L.lds, h->stream, A, B, Prec<T>::tw(h, 1),
                        h->geo, h->plan[1], L.tile, L.lstride);
   else
     hipLaunchKernelGGL((k_ypass<T, kEPT, +1>), grid, dim3(L.nthr), L.lds, h->stream, B, A, Prec<T>::tw(h, 1),
                        h->geo, h->plan[1], L.tile, L.lstride);
+  stage_end(h, stage);
 }
 
 // forward FFT of nf real FP64 fields (MODE 0) or of 2 S g_c (MODE 1), through z, y, x; then the
@@ -314,27 +352,34 @@ void enqueue_spectral(vdwxc_ctx* h, int mode, const double* src, const double* a
   Geometry g = h->geo;
   g.M = nin;
   dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
+  const int s0 = mode == 0 ? VDWXC_STAGE_GRAD_Z : VDWXC_STAGE_DIV_Z;
+  stage_begin(h);
   if (mode == 0)
     hipLaunchKernelGGL((k_real_zfwd<T, kEPT, 0>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, src, aux, nin, A,
                        Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
   else
     hipLaunchKernelGGL((k_real_zfwd<T, kEPT, 1>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, src, aux, nin, A,
                        Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
-  enqueue_ypass<T>(h, nin, -1);
+  stage_end(h, s0);
+  enqueue_ypass<T>(h, nin, -1, s0 + 1);
   dim3 xgrid(h->n2, h->h3);
+  stage_begin(h);
   if (nin == 1)
     hipLaunchKernelGGL((k_xspectral<T, kEPTX, 1, 3>), xgrid, dim3(Lx.nthr), Lx.lds, h->stream, B,
                        Prec<T>::tw(h, 0), g, h->plan[0]);
   else
     hipLaunchKernelGGL((k_xspectral<T, kEPTX, 3, 1>), xgrid, dim3(Lx.nthr), Lx.lds, h->stream, B,
                        Prec<T>::tw(h, 0), g, h->plan[0]);
-  enqueue_ypass<T>(h, nout, +1);
+  stage_end(h, s0 + 2);
+  enqueue_ypass<T>(h, nout, +1, s0 + 3);
+  stage_begin(h);
   if (nout == 3)
     hipLaunchKernelGGL((k_real_zinv<T, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, nout, out,
                        Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
   else
     hipLaunchKernelGGL((k_real_zinv<T, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, nout, out,
                        Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
+  stage_end(h, s0 + 4);
 }
 
 // the five steps: theta + z FFT, y FFT, x FFT + contraction + inverse x, inverse y, inverse z +
@@ -348,16 +393,21 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   T2* A = static_cast<T2*>(h->d_A);
   T2* B = static_cast<T2*>(h->d_B);
   dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
+  stage_begin(h);
   if (sig_from_grad)
     hipLaunchKernelGGL((k_theta_zfwd<T, kPPT, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, n, sig, A,
                        h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
   else
     hipLaunchKernelGGL((k_theta_zfwd<T, kPPT, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, n, sig, A,
                        h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
-  enqueue_ypass<T>(h, h->M, -1);
+  stage_end(h, VDWXC_STAGE_THETA_ZFWD);
+  enqueue_ypass<T>(h, h->M, -1, VDWXC_STAGE_Y_FWD);
+  stage_begin(h);
   hipLaunchKernelGGL((k_xcontract<T, kEPTX>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
                      Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
-  enqueue_ypass<T>(h, h->M, +1);
+  stage_end(h, VDWXC_STAGE_X_CONTRACT);
+  enqueue_ypass<T>(h, h->M, +1, VDWXC_STAGE_Y_INV);
+  stage_begin(h);
   if (sig_from_grad)
     hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, n,
                        sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile,
@@ -366,9 +416,12 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
     hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, n,
                        sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile,
                        Lz.lstride);
+  stage_end(h, VDWXC_STAGE_Z_ASSEMBLE);
   const double N = double(h->n1) * h->n2 * h->n3;
+  stage_begin(h);
   hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(512), 0, h->stream, h->d_partials, h->n2 * h->h3,
                      h->omega / (2.0 * N * N), h->d_flag, energy);
+  stage_end(h, VDWXC_STAGE_ENERGY);
 }
 
 vdwxc_status check_handle(vdwxc_ctx* h) {
@@ -646,6 +699,48 @@ vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const do
   vdwxc_status st = run_potential(h, n, grad_n, v, h->d_energy);
   if (st != VDWXC_OK) return st;
   return read_energy(h, energy_host);
+}
+
+const char* vdwxc_stage_name(int stage) {
+  static const char* names[VDWXC_NUM_STAGES] = {
+      "theta_zfwd", "y_fwd", "x_contract", "y_inv", "z_assemble", "energy", "grad_z", "grad_y",
+      "grad_x", "grad_yi", "grad_zi", "div_z", "div_y", "div_x", "div_yi", "div_zi"};
+  return (stage >= 0 && stage < VDWXC_NUM_STAGES) ? names[stage] : "?";
+}
+
+vdwxc_status vdwxc_enable_timing(vdwxc_handle h, int enable) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (auto& p : h->pending) {
+    h->free_events.push_back(p.start);
+    h->free_events.push_back(p.stop);
+  }
+  h->pending.clear();
+  for (int i = 0; i < VDWXC_NUM_STAGES; ++i) { h->stage_ms[i] = 0.0; h->stage_count[i] = 0; }
+  h->timing = enable != 0;
+  return VDWXC_OK;
+}
+
+vdwxc_status vdwxc_read_timing(vdwxc_handle h, double* ms, long long* launches) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (!ms || !launches) return fail(h, VDWXC_EINVAL, "timing arrays must not be NULL");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (auto& p : h->pending) {
+    float t = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&t, p.start, p.stop));
+    h->stage_ms[p.stage] += t;
+    h->stage_count[p.stage] += 1;
+    h->free_events.push_back(p.start);
+    h->free_events.push_back(p.stop);
+  }
+  h->pending.clear();
+  for (int i = 0; i < VDWXC_NUM_STAGES; ++i) {
+    ms[i] = h->stage_ms[i];
+    launches[i] = h->stage_count[i];
+    h->stage_ms[i] = 0.0;
+    h->stage_count[i] = 0;
+  }
+  return VDWXC_OK;
 }
 
 vdwxc_status vdwxc_set_stream(vdwxc_handle h, void* hip_stream) {

@@ -45,7 +45,11 @@ SIGNATURES = {
     "vdwxc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "vdwxc_last_error": (ctypes.c_char_p, [_h]),
     "vdwxc_version": (ctypes.c_char_p, []),
+    "vdwxc_enable_timing": (ctypes.c_int, [_h, ctypes.c_int]),
+    "vdwxc_read_timing": (ctypes.c_int, [_h, _dp, ctypes.POINTER(ctypes.c_longlong)]),
+    "vdwxc_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
 }
+NUM_STAGES = 16
 
 _lib = None
 
@@ -185,6 +189,18 @@ class Functional:
         st = lib().vdwxc_calculate_potential_async(self._h, self._field(n, "n"), gp, self._field(v, "v"),
                                                    ctypes.c_void_p(energy.data_ptr()))
         _check(st, self._h)
+
+    def enable_timing(self, enable: bool = True):
+        """Record HIP events around every kernel launch of this handle (see read_timing)."""
+        _check(lib().vdwxc_enable_timing(self._h, int(bool(enable))), self._h)
+
+    def read_timing(self):
+        """{stage name: (total ms, launches)} since the last enable/read; synchronises."""
+        ms = (ctypes.c_double * NUM_STAGES)()
+        cnt = (ctypes.c_longlong * NUM_STAGES)()
+        _check(lib().vdwxc_read_timing(self._h, ms, cnt), self._h)
+        L = lib()
+        return {L.vdwxc_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NUM_STAGES) if cnt[i] > 0}
 
     def set_stream(self, stream):
         self._stream = stream
