@@ -198,24 +198,34 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
 }
 
 // Transform `nlines` LDS lines of length plan.n.  Requires nlines * n <= nthr * EPT.  The caller
-// must have synchronised after filling the lines; the lines are complete on return.
+// must have synchronised after filling the lines; the lines are complete on return.  The plan
+// lists its radices grouped (all 8s, then 4, 2, 3s, 5s, 7s), so each radix runs in its own loop
+// and the register allocation of one stage kind does not inflate the others.
+template <int R, int EPT, int DIR, typename T2>
+__device__ __forceinline__ void run_stages(T2* buf, int n, int count, int& p, int nlines, int lstride,
+                                           const T2* __restrict__ tw, int tid, int nthr) {
+  for (int s = 0; s < count; ++s) {
+    fft_stage<R, (EPT + R - 1) / R, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr);
+    p *= R;
+  }
+}
+
 template <int EPT, int DIR, typename T2>
 __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
                         const T2* __restrict__ tw, int tid, int nthr) {
   const int n = plan.n;
-  int p = 1;
+  int cnt[6] = {0, 0, 0, 0, 0, 0};   // radix 8, 4, 2, 3, 5, 7
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.radix[s];
-    switch (R) {
-      case 8: fft_stage<8, (EPT + 7) / 8, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
-      case 4: fft_stage<4, (EPT + 3) / 4, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
-      case 2: fft_stage<2, (EPT + 1) / 2, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
-      case 3: fft_stage<3, (EPT + 2) / 3, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
-      case 5: fft_stage<5, (EPT + 4) / 5, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
-      default: fft_stage<7, (EPT + 6) / 7, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr); break;
-    }
-    p *= R;
+    cnt[R == 8 ? 0 : R == 4 ? 1 : R == 2 ? 2 : R == 3 ? 3 : R == 5 ? 4 : 5] += 1;
   }
+  int p = 1;
+  run_stages<8, EPT, DIR>(buf, n, cnt[0], p, nlines, lstride, tw, tid, nthr);
+  run_stages<4, EPT, DIR>(buf, n, cnt[1], p, nlines, lstride, tw, tid, nthr);
+  run_stages<2, EPT, DIR>(buf, n, cnt[2], p, nlines, lstride, tw, tid, nthr);
+  run_stages<3, EPT, DIR>(buf, n, cnt[3], p, nlines, lstride, tw, tid, nthr);
+  run_stages<5, EPT, DIR>(buf, n, cnt[4], p, nlines, lstride, tw, tid, nthr);
+  run_stages<7, EPT, DIR>(buf, n, cnt[5], p, nlines, lstride, tw, tid, nthr);
 }
 
 }  // namespace vdwxc

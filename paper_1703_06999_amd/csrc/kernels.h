@@ -34,6 +34,7 @@ struct Geometry {
   double bvec[9];          // reciprocal vectors b1, b2, b3 (rows), bohr^-1
   double kmax, inv_dk;     // kernel table range and inverse node spacing
   int nk;                  // kernel table nodes
+  double bn2[3];           // |b_i|^2 (used when the cell is orthogonal)
 };
 
 // ---- q0, saturation and the helper splines (per grid point, FP64) ----------------------------
@@ -96,23 +97,6 @@ __device__ __forceinline__ void q0_state(double n, double sigma, double zab, con
   t = (q0 - q[b]) / (q[b + 1] - q[b]);
 }
 
-// Natural cubic spline through p_a(q_b) = delta_ab with second derivatives mm[a][b]:
-//   p_a = (1-t) d_ab + t d_a,b+1 + h^2/6 [((1-t)^3-(1-t)) mm_ab + (t^3-t) mm_a,b+1]
-__device__ __forceinline__ double spline_p(int a, int b, double t, double h, const double* mm, int M) {
-  const double u = 1.0 - t;
-  double p = h * h * (1.0 / 6.0) * ((u * u * u - u) * mm[a * M + b] + (t * t * t - t) * mm[a * M + b + 1]);
-  if (a == b) p += u;
-  if (a == b + 1) p += t;
-  return p;
-}
-__device__ __forceinline__ double spline_dp(int a, int b, double t, double h, const double* mm, int M) {
-  const double u = 1.0 - t;
-  double d = h * (1.0 / 6.0) * (-(3.0 * u * u - 1.0) * mm[a * M + b] + (3.0 * t * t - 1.0) * mm[a * M + b + 1]);
-  if (a == b) d -= 1.0 / h;
-  if (a == b + 1) d += 1.0 / h;
-  return d;
-}
-
 __device__ __forceinline__ size_t a_index(const Geometry& g, int f, int kz, int x, int y) {
   return ((size_t(f) * g.h3 + kz) * g.n1 + x) * g.n2 + y;
 }
@@ -130,76 +114,152 @@ __device__ __forceinline__ void split_pair(T2 zk, T2 zn, T2& xa, T2& xb) {
   xb = T2{half * (zk.y + zn.y), half * (zn.x - zk.x)};
 }
 
-// ---- pass 1: q0 + splines + forward z FFT (theta fields) ------------------------------------
-// Block: one x plane, TY consecutive y lines (blockIdx.x = y tile, blockIdx.y = x).
+// ---- XCD-aware block order ---------------------------------------------------------------------
+// The dispatcher hands block b to XCD b mod 8, and each XCD has its own L2.  Remapping the linear
+// block id so that consecutive logical tiles land on the same XCD lets the two blocks that write
+// the halves of one cache line merge them in one L2.
+__device__ __forceinline__ int xcd_logical_block(int b, int nb) {
+  const int per = nb >> 3;
+  if (b >= (per << 3)) return b;
+  return (b & 7) * per + (b >> 3);
+}
 
-template <typename T, int PPT, int EPT, bool SIGMA_FROM_GRAD>
-__global__ void __launch_bounds__(512)
+// logical (tile, x) of a z-pass block; grid = (ntiles, n1)
+__device__ __forceinline__ void zpass_block(int& tile, int& x) {
+  const int nb = gridDim.x * gridDim.y;
+  const int L = xcd_logical_block(blockIdx.x + gridDim.x * blockIdx.y, nb);
+  tile = L % gridDim.x;
+  x = L / gridDim.x;
+}
+
+// ---- per-point spline state in LDS --------------------------------------------------------------
+// Natural cubic spline on interval b (h = q_{b+1} - q_b, c6 = h^2/6) with second derivatives mm:
+//   p_a  = (1-t) d_ab + t d_a,b+1 + c6 [((1-t)^3-(1-t)) mm_ab + (t^3-t) mm_a,b+1]
+//   p_a' = (d_a,b+1 - d_ab)/h + (h/6) [-(3(1-t)^2-1) mm_ab + (3t^2-1) mm_a,b+1]
+// mmT holds mm transposed ([b][a]) so that the two fields of a pair are adjacent.
+template <typename T>
+struct SplineLds {
+  T* mmT;      // [M][M]
+  T* h;        // [M-1]
+  T* c6;       // [M-1]
+  double* q;   // [M]
+  __device__ __forceinline__ T p(int a, int b, T t) const {
+    const T u = T(1) - t;
+    T v = c6[b] * ((u * u * u - u) * mmT[b * kMaxQ + a] + (t * t * t - t) * mmT[(b + 1) * kMaxQ + a]);
+    if (a == b) v += u;
+    if (a == b + 1) v += t;
+    return v;
+  }
+  __device__ __forceinline__ T dp(int a, int b, T t) const {
+    const T u = T(1) - t;
+    const T hh = h[b];
+    T v = hh * T(1.0 / 6.0) * (-(T(3) * u * u - T(1)) * mmT[b * kMaxQ + a] + (T(3) * t * t - T(1)) * mmT[(b + 1) * kMaxQ + a]);
+    if (a == b) v -= T(1) / hh;
+    if (a == b + 1) v += T(1) / hh;
+    return v;
+  }
+};
+
+// carve the shared tables out of LDS (after `off` bytes) and fill them from global memory
+template <typename T>
+__device__ __forceinline__ SplineLds<T> load_spline_lds(unsigned char* smem, size_t off, const double* qmesh,
+                                                        const double* mm, int M, int tid, int nthr) {
+  SplineLds<T> S;
+  S.q = reinterpret_cast<double*>(smem + off);
+  S.mmT = reinterpret_cast<T*>(smem + off + kMaxQ * sizeof(double));
+  S.h = S.mmT + kMaxQ * kMaxQ;
+  S.c6 = S.h + kMaxQ;
+  for (int i = tid; i < M; i += nthr) S.q[i] = qmesh[i];
+  for (int i = tid; i < M * M; i += nthr) {
+    const int a = i / M, b = i - a * M;
+    S.mmT[b * kMaxQ + a] = T(mm[i]);
+  }
+  for (int i = tid; i < M - 1; i += nthr) {
+    const double hh = qmesh[i + 1] - qmesh[i];
+    S.h[i] = T(hh);
+    S.c6[i] = T(hh * hh / 6.0);
+  }
+  return S;
+}
+
+// bytes of the spline tables in LDS
+template <typename T>
+constexpr size_t spline_lds_bytes() {
+  return kMaxQ * sizeof(double) + (kMaxQ * kMaxQ + 2 * kMaxQ) * sizeof(T);
+}
+
+__device__ __forceinline__ double point_sigma(const double* __restrict__ sig, size_t idx, size_t N, bool from_grad) {
+  if (from_grad) {
+    const double gx = sig[idx], gy = sig[N + idx], gz = sig[2 * N + idx];
+    return gx * gx + gy * gy + gz * gz;
+  }
+  return sig[idx];
+}
+
+// ---- pass 1: q0 + splines + forward z FFT (theta fields) ------------------------------------
+// Block: one x plane, TY consecutive y lines.  LDS: the TY pair lines, then per point the spline
+// interval b (uint8, 255 = vacuum), position t and density n, then the spline tables.  q0 is
+// evaluated once per point in FP64; theta_a = n p_a(q0) is formed in the path's precision T.
+
+template <typename T, int EPT, bool SIGMA_FROM_GRAD>
+__global__ void __launch_bounds__(1024)
 k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
              typename Cx<T>::type* __restrict__ A, int* __restrict__ flag,
              const double* __restrict__ qmesh, const double* __restrict__ mm,
              const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double s_q[kMaxQ];
-  __shared__ double s_mm[kMaxQ * kMaxQ];
-  T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int x = blockIdx.y, y0 = blockIdx.x * ty;
+  int tile, x;
+  zpass_block(tile, x);
+  const int y0 = tile * ty;
   const int n3 = g.n3, M = g.M;
   const size_t N = size_t(g.n1) * g.n2 * n3;
-  for (int i = tid; i < M; i += nthr) s_q[i] = qmesh[i];
-  for (int i = tid; i < M * M; i += nthr) s_mm[i] = mm[i];
+  const int npts = ty * n3;
+  T2* line = reinterpret_cast<T2*>(smem);
+  size_t off = size_t(ty) * lstride * sizeof(T2);
+  T* st_t = reinterpret_cast<T*>(smem + off);
+  off += size_t(npts) * sizeof(T);
+  T* st_n = reinterpret_cast<T*>(smem + off);
+  off += size_t(npts) * sizeof(T);
+  unsigned char* st_b = smem + off;
+  off += (size_t(npts) + 15) & ~size_t(15);
+  const SplineLds<T> S = load_spline_lds<T>(smem, off, qmesh, mm, M, tid, nthr);
   __syncthreads();
 
-  const int npts = ty * n3;
-  int pb[PPT];
-  double pt[PPT], pn[PPT];
   bool bad = false;
-#pragma unroll
-  for (int c = 0; c < PPT; ++c) {
-    const int p = tid + c * nthr;
-    pb[c] = -1;
-    pt[c] = 0.0;
-    pn[c] = 0.0;
-    if (p < npts) {
-      const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
-      if (y < g.n2) {
-        const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-        const double nv = nden[idx];
-        double sv;
-        if (SIGMA_FROM_GRAD) {
-          const double gx = sig[idx], gy = sig[N + idx], gz = sig[2 * N + idx];
-          sv = gx * gx + gy * gy + gz * gz;
-        } else {
-          sv = sig[idx];
-        }
-        bad |= !(nv == nv) || !(sv == sv);
-        double d1, d2;
-        q0_state(nv, sv, g.zab, s_q, M, pb[c], pt[c], d1, d2);
-        pn[c] = nv;
-      }
+  for (int p = tid; p < npts; p += nthr) {
+    const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+    int b = -1;
+    double t = 0.0, nv = 0.0;
+    if (y < g.n2) {
+      const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
+      nv = nden[idx];
+      const double sv = point_sigma(sig, idx, N, SIGMA_FROM_GRAD);
+      bad |= !(nv == nv) || !(sv == sv);
+      double d1, d2;
+      q0_state(nv, sv, g.zab, S.q, M, b, t, d1, d2);
     }
+    st_b[p] = b < 0 ? 255 : (unsigned char)b;
+    st_t[p] = T(t);
+    st_n[p] = T(nv);
   }
   if (bad) *flag = 1;
+  __syncthreads();
 
   const int npairs = (M + 1) >> 1;
   for (int pr = 0; pr < npairs; ++pr) {
     const int fa = 2 * pr, fb = 2 * pr + 1;
-#pragma unroll
-    for (int c = 0; c < PPT; ++c) {
-      const int p = tid + c * nthr;
-      if (p < npts) {
-        const int yl = p / n3, z = p - yl * n3;
-        double ta = 0.0, tb = 0.0;
-        const int b = pb[c];
-        if (b >= 0) {
-          const double h = s_q[b + 1] - s_q[b];
-          ta = pn[c] * spline_p(fa, b, pt[c], h, s_mm, M);
-          if (fb < M) tb = pn[c] * spline_p(fb, b, pt[c], h, s_mm, M);
-        }
-        line[yl * lstride + z] = T2{T(ta), T(tb)};
+    for (int p = tid; p < npts; p += nthr) {
+      const int yl = p / n3, z = p - yl * n3;
+      const int b = st_b[p];
+      T ta = T(0), tb = T(0);
+      if (b != 255) {
+        const T t = st_t[p], nv = st_n[p];
+        ta = nv * S.p(fa, b, t);
+        if (fb < M) tb = nv * S.p(fb, b, t);
       }
+      line[yl * lstride + z] = T2{ta, tb};
     }
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, tw, tid, nthr);
@@ -224,7 +284,7 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
 // input), S = dE/dsigma (src) and g the gradient (aux, [3][N]).
 
 template <typename T, int EPT, int MODE>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int nf,
             typename Cx<T>::type* __restrict__ A, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan zp, int ty, int lstride) {
@@ -232,7 +292,9 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
   extern __shared__ __align__(16) unsigned char smem[];
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int x = blockIdx.y, y0 = blockIdx.x * ty;
+  int tile, x;
+  zpass_block(tile, x);
+  const int y0 = tile * ty;
   const int n3 = g.n3;
   const size_t N = size_t(g.n1) * g.n2 * n3;
   const int npts = ty * n3;
@@ -276,14 +338,16 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
 // Block: TX consecutive x of one (f, kz) (blockIdx.x = x tile, .y = kz, .z = f).
 
 template <typename T, int EPT, int DIR>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __restrict__ dst,
         const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan yp, int tx, int lstride) {
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int x0 = blockIdx.x * tx, kz = blockIdx.y, f = blockIdx.z;
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  const int L = xcd_logical_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+  const int x0 = (L % gridDim.x) * tx, kz = (L / gridDim.x) % gridDim.y, f = L / (gridDim.x * gridDim.y);
   const int n2 = g.n2, tot = tx * n2;
   if (DIR < 0) {
     const size_t base = a_index(g, f, kz, x0, 0);
@@ -334,12 +398,22 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 
 // ---- pass 3: x FFT, k-space contraction, inverse x FFT (in place in B) -----------------------
 // Block: the M field lines of one (ky, kz) column (blockIdx.x = ky, .y = kz).
-// Per k: phi_ab = (1-w) T_j,ab + w T_j+1,ab with |G| = (j + w) dk; F_a = sum_b phi_ab theta_b;
-// energy weight 2 for kz strictly inside the half spectrum, 1 on its edges.
+// Per k: phi_ab = (1-w) T_j,ab + w T_j+1,ab with |G| = (j + w) dk (Sec. 3 step 3a);
+// F_a = sum_b phi_ab theta_b (step 3b); energy sum_a Re theta_a* F_a (step 3c), weight 2 for kz
+// strictly inside the half spectrum, 1 on its edges.  The table is stored per unordered pair
+// (a <= b) as (T_j, T_j+1) with j contiguous, so one 2-element load gives both nodes of the lerp
+// and lanes with nearby |G| share cache lines.  F is formed one row a at a time, so the M loads
+// of a row are independent and in flight together.
+// NPT = 2: in an orthogonal cell |G(kx)| = |G(-kx)|, so a thread handles kx and -kx with one
+// interpolated kernel.
 
-template <typename T, int EPT>
+// pair index of (a <= b) for a table dimensioned by kMaxQ
+__host__ __device__ constexpr int pair_index(int a, int b) { return a * kMaxQ - a * (a - 1) / 2 + (b - a); }
+constexpr int kNumPairs = kMaxQ * (kMaxQ + 1) / 2;
+
+template <typename T, int EPT, int NPT>
 __global__ void __launch_bounds__(512)
-k_xcontract(typename Cx<T>::type* __restrict__ B, const T* __restrict__ table,
+k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ table2,
             double* __restrict__ partials, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
   using T2 = typename Cx<T>::type;
@@ -356,40 +430,70 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const T* __restrict__ table,
   for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1>(line + l0 * n1, xp, min(G, M - l0), n1, tw, tid, nthr);
 
   const double wz = (kz == 0 || is_nyquist(kz, g.n3)) ? 1.0 : 2.0;
-  const int MM = M * M;
+  const double fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
+  const double g2yz = fy * fy * g.bn2[1] + fz * fz * g.bn2[2];
+  const int nslots = NPT == 2 ? n1 / 2 + 1 : n1;
   double esum = 0.0;
-  for (int kx = tid; kx < n1; kx += nthr) {
-    const double kn = sqrt(gnorm2(g, kx, ky, kz));
-    T2 th[kMaxQ];
-#pragma unroll
-    for (int b = 0; b < kMaxQ; ++b) th[b] = b < M ? line[b * n1 + kx] : T2{T(0), T(0)};
+  for (int s = tid; s < nslots; s += nthr) {
+    int kx[NPT];
+    bool valid[NPT];
+    kx[0] = s;
+    valid[0] = true;
+    double kn;
+    if (NPT == 2) {
+      kx[NPT - 1] = (n1 - s) % n1;
+      valid[NPT - 1] = (s != 0) && (2 * s != n1);
+      const double fx = double(s);
+      kn = sqrt(fx * fx * g.bn2[0] + g2yz);
+    } else {
+      kn = sqrt(gnorm2(g, s, ky, kz));
+    }
     const bool inside = kn < g.kmax;
-    const double s = kn * g.inv_dk;
-    int j = inside ? int(floor(s)) : 0;
+    const double sc = kn * g.inv_dk;
+    int j = inside ? int(floor(sc)) : 0;
     if (j > g.nk - 2) j = g.nk - 2;
-    const T w = T(inside ? s - j : 0.0);
+    const T w = T(inside ? sc - j : 0.0);
     const T w0 = inside ? T(1) - w : T(0);
     const T w1 = inside ? w : T(0);
-    const T* t0 = table + size_t(j) * MM;
-    const T* t1 = t0 + MM;
-    double e = 0.0;
+    T2 th[NPT][kMaxQ];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+#pragma unroll
+      for (int a = 0; a < kMaxQ; ++a) th[q][a] = (a < M && valid[q]) ? line[a * n1 + kx[q]] : T2{T(0), T(0)};
+    }
+    const T2* tp = table2 + j;
+    T e[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) e[q] = T(0);
+    // one row a at a time: its M table entries are independent loads that can all be in flight
 #pragma unroll
     for (int a = 0; a < kMaxQ; ++a) {
       if (a < M) {
-        T2 F = T2{T(0), T(0)};
+        T2 row[kMaxQ];
+#pragma unroll
+        for (int b = 0; b < kMaxQ; ++b)
+          row[b] = b < M ? tp[size_t(a <= b ? pair_index(a, b) : pair_index(b, a)) * g.nk] : T2{T(0), T(0)};
+        T2 F[NPT];
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) F[q] = T2{T(0), T(0)};
 #pragma unroll
         for (int b = 0; b < kMaxQ; ++b) {
-          if (b < M) {
-            const T phi = w0 * t0[a * M + b] + w1 * t1[a * M + b];
-            F.x += phi * th[b].x;
-            F.y += phi * th[b].y;
+          const T phi = w0 * row[b].x + w1 * row[b].y;
+#pragma unroll
+          for (int q = 0; q < NPT; ++q) {
+            F[q].x += phi * th[q][b].x;
+            F[q].y += phi * th[q][b].y;
           }
         }
-        e += double(th[a].x) * double(F.x) + double(th[a].y) * double(F.y);
-        line[a * n1 + kx] = F;
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+          e[q] += th[q][a].x * F[q].x + th[q][a].y * F[q].y;
+          if (valid[q]) line[a * n1 + kx[q]] = F[q];
+        }
       }
     }
-    esum += wz * e;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) esum += wz * double(e[q]);
   }
   __syncthreads();
   for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1>(line + l0 * n1, xp, min(G, M - l0), n1, tw, tid, nthr);
@@ -404,9 +508,9 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const T* __restrict__ table,
   if ((tid & 63) == 0) red[tid >> 6] = esum;
   __syncthreads();
   if (tid == 0) {
-    double s = 0.0;
-    for (int w = 0; w < (nthr + 63) / 64; ++w) s += red[w];
-    partials[size_t(kz) * g.n2 + ky] = s;
+    double sum = 0.0;
+    for (int wv = 0; wv < (nthr + 63) / 64; ++wv) sum += red[wv];
+    partials[size_t(kz) * g.n2 + ky] = sum;
   }
 }
 
@@ -490,52 +594,56 @@ __device__ __forceinline__ void load_pair_line(const T2* __restrict__ A, const G
 }
 
 // ---- pass 5: inverse z FFT + assembly of dE/dn, dE/dsigma (eqs. dedn, dedsigma) -------------
+// dE/dn = sum_a F_a [p_a + n p_a' dq0/dn],  dE/dsigma = sum_a F_a n p_a' dq0/dsigma, with F_a(r)
+// from the inverse transforms (1/N applied here).  q0 is recomputed once per point in FP64; the
+// per-point spline state (b, t, n dq0/dn, n dq0/dsigma) sits in LDS, the two sums in FP64
+// registers.
 
 template <typename T, int PPT, int EPT, bool SIGMA_FROM_GRAD>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __restrict__ nden,
                 const double* __restrict__ sig, double* __restrict__ dedn, double* __restrict__ dedsig,
                 const double* __restrict__ qmesh, const double* __restrict__ mm,
                 const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double s_q[kMaxQ];
-  __shared__ double s_mm[kMaxQ * kMaxQ];
-  T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int x = blockIdx.y, y0 = blockIdx.x * ty;
+  int tile, x;
+  zpass_block(tile, x);
+  const int y0 = tile * ty;
   const int n3 = g.n3, M = g.M;
   const size_t N = size_t(g.n1) * g.n2 * n3;
-  for (int i = tid; i < M; i += nthr) s_q[i] = qmesh[i];
-  for (int i = tid; i < M * M; i += nthr) s_mm[i] = mm[i];
+  const int npts = ty * n3;
+  T2* line = reinterpret_cast<T2*>(smem);
+  size_t off = size_t(ty) * lstride * sizeof(T2);
+  T* st_t = reinterpret_cast<T*>(smem + off);
+  off += size_t(npts) * sizeof(T);
+  T* st_an = reinterpret_cast<T*>(smem + off);
+  off += size_t(npts) * sizeof(T);
+  T* st_as = reinterpret_cast<T*>(smem + off);
+  off += size_t(npts) * sizeof(T);
+  unsigned char* st_b = smem + off;
+  off += (size_t(npts) + 15) & ~size_t(15);
+  const SplineLds<T> S = load_spline_lds<T>(smem, off, qmesh, mm, M, tid, nthr);
   __syncthreads();
 
-  const int npts = ty * n3;
-  int pb[PPT];
-  double pt[PPT], pdn[PPT], pds[PPT], acc_n[PPT], acc_s[PPT];
-#pragma unroll
-  for (int c = 0; c < PPT; ++c) {
-    const int p = tid + c * nthr;
-    pb[c] = -1;
-    pt[c] = pdn[c] = pds[c] = 0.0;
-    acc_n[c] = acc_s[c] = 0.0;
-    if (p < npts) {
-      const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
-      if (y < g.n2) {
-        const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-        const double nv = nden[idx];
-        double sv;
-        if (SIGMA_FROM_GRAD) {
-          const double gx = sig[idx], gy = sig[N + idx], gz = sig[2 * N + idx];
-          sv = gx * gx + gy * gy + gz * gz;
-        } else {
-          sv = sig[idx];
-        }
-        q0_state(nv, sv, g.zab, s_q, M, pb[c], pt[c], pdn[c], pds[c]);
-      }
+  for (int p = tid; p < npts; p += nthr) {
+    const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+    int b = -1;
+    double t = 0.0, an = 0.0, as = 0.0;
+    if (y < g.n2) {
+      const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
+      q0_state(nden[idx], point_sigma(sig, idx, N, SIGMA_FROM_GRAD), g.zab, S.q, M, b, t, an, as);
     }
+    st_b[p] = b < 0 ? 255 : (unsigned char)b;
+    st_t[p] = T(t);
+    st_an[p] = T(an);
+    st_as[p] = T(as);
   }
 
+  double acc_n[PPT], acc_s[PPT];
+#pragma unroll
+  for (int c = 0; c < PPT; ++c) acc_n[c] = acc_s[c] = 0.0;
   const int npairs = (M + 1) >> 1;
   for (int pr = 0; pr < npairs; ++pr) {
     const int fa = 2 * pr, fb = 2 * pr + 1 < M ? 2 * pr + 1 : -1;
@@ -545,20 +653,22 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
 #pragma unroll
     for (int c = 0; c < PPT; ++c) {
       const int p = tid + c * nthr;
-      const int b = pb[c];
-      if (p < npts && b >= 0) {
-        const int yl = p / n3, z = p - yl * n3;
-        const T2 F = line[yl * lstride + z];
-        const double h = s_q[b + 1] - s_q[b];
-        const double pa = spline_p(fa, b, pt[c], h, s_mm, M);
-        const double dpa = spline_dp(fa, b, pt[c], h, s_mm, M);
-        acc_n[c] += double(F.x) * (pa + pdn[c] * dpa);
-        acc_s[c] += double(F.x) * (pds[c] * dpa);
-        if (fb >= 0) {
-          const double pbv = spline_p(fb, b, pt[c], h, s_mm, M);
-          const double dpb = spline_dp(fb, b, pt[c], h, s_mm, M);
-          acc_n[c] += double(F.y) * (pbv + pdn[c] * dpb);
-          acc_s[c] += double(F.y) * (pds[c] * dpb);
+      if (p < npts) {
+        const int b = st_b[p];
+        if (b != 255) {
+          const int yl = p / n3, z = p - yl * n3;
+          const T2 F = line[yl * lstride + z];
+          const T t = st_t[p], an = st_an[p], as = st_as[p];
+          const T pa = S.p(fa, b, t), dpa = S.dp(fa, b, t);
+          T vn = F.x * (pa + an * dpa);
+          T vs = F.x * (as * dpa);
+          if (fb >= 0) {
+            const T pbv = S.p(fb, b, t), dpb = S.dp(fb, b, t);
+            vn += F.y * (pbv + an * dpb);
+            vs += F.y * (as * dpb);
+          }
+          acc_n[c] += double(vn);
+          acc_s[c] += double(vs);
         }
       }
     }
@@ -582,14 +692,16 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
 // ---- pass 5 for plain real fields: out[f] = IFFT/N (COMBINE: out[0] -= IFFT/N) -------------
 
 template <typename T, int EPT, bool COMBINE>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(1024)
 k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restrict__ out,
             const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int x = blockIdx.y, y0 = blockIdx.x * ty;
+  int tile, x;
+  zpass_block(tile, x);
+  const int y0 = tile * ty;
   const int n3 = g.n3;
   const size_t N = size_t(g.n1) * g.n2 * n3;
   const double invN = 1.0 / double(N);

@@ -23,11 +23,12 @@ using namespace vdwxc;
 
 namespace {
 
-constexpr int kPPT = 8;        // grid points per thread in the z passes
-constexpr int kEPT = 8;        // FFT elements per thread in the z and y passes
-constexpr int kEPTX = 8;       // FFT elements per thread in the x passes
-constexpr int kMaxThreads = 512;
-constexpr int kLineTile = 16;  // lines per block in the z and y passes
+constexpr int kPPT = 4;          // grid points per thread in the z passes
+constexpr int kEPT = 4;          // FFT elements per thread in the z and y passes
+constexpr int kEPTX = 8;         // FFT elements per thread in the x passes
+constexpr int kMaxThreads = 1024;  // z and y passes
+constexpr int kMaxThreadsX = 256;  // x passes (large register footprint of the contraction)
+constexpr int kLineTile = 16;    // lines per block in the z and y passes
 constexpr size_t kMaxLds = 160 * 1024;
 
 thread_local std::string g_init_error;
@@ -53,11 +54,13 @@ struct vdwxc_ctx {
   Geometry geo{};
   AxisPlan plan[3]{};
   Launch zl64, zl32, yl64, yl32, xl64, xl32, xs64, xs32;
+  size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
+  bool ortho = false;
   // device memory
   double* d_q = nullptr;
   double* d_mm = nullptr;
-  double* d_table64 = nullptr;
-  float* d_table32 = nullptr;
+  double2* d_table64 = nullptr;   // [pair][j] = (T_j, T_j+1)
+  float2* d_table32 = nullptr;
   double2* d_tw64[3] = {nullptr, nullptr, nullptr};
   float2* d_tw32[3] = {nullptr, nullptr, nullptr};
   void* d_A = nullptr;
@@ -218,14 +221,22 @@ bool line_launch(int nlines_max, int n, int other, size_t cplx_bytes, Launch& L)
   return L.lds + 4096 <= kMaxLds;
 }
 
-bool xline_launch(int nlines, int n, size_t cplx_bytes, Launch& L) {
-  // all field lines of one column in LDS, transformed in groups of nthr * EPT / n lines
-  if (n > kMaxThreads * kEPTX) return false;
+
+bool xline_launch(int nlines, int n, int slots, size_t cplx_bytes, Launch& L) {
+  // all field lines of one column in LDS, transformed in groups of nthr * EPT / n lines; one
+  // thread per contraction slot up to kMaxThreadsX
   L.tile = nlines;
-  L.nthr = threads_for(long(nlines) * n, kEPTX);
+  L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(slots, 64)));
+  if (n > L.nthr * kEPTX) return false;
   L.lstride = n;
   L.lds = std::max<size_t>(size_t(nlines) * n * cplx_bytes, 16 * sizeof(double));
   return L.lds <= kMaxLds;
+}
+
+template <typename T>
+size_t zstate_lds(const Launch& L, int n3, int per_point_values) {
+  const size_t npts = size_t(L.tile) * n3;
+  return L.lds + npts * per_point_values * sizeof(T) + ((npts + 15) & ~size_t(15)) + spline_lds_bytes<T>();
 }
 
 size_t complex_buffer_bytes(int n1, int n2, int n3, vdwxc_precision p, int M) {
@@ -285,7 +296,9 @@ template <> struct Prec<double> {
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs64; }
   static const double2* tw(const vdwxc_ctx* h, int a) { return h->d_tw64[a]; }
-  static const double* table(const vdwxc_ctx* h) { return h->d_table64; }
+  static const double2* table(const vdwxc_ctx* h) { return h->d_table64; }
+  static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta64; }
+  static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm64; }
 };
 template <> struct Prec<float> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl32; }
@@ -293,7 +306,9 @@ template <> struct Prec<float> {
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs32; }
   static const float2* tw(const vdwxc_ctx* h, int a) { return h->d_tw32[a]; }
-  static const float* table(const vdwxc_ctx* h) { return h->d_table32; }
+  static const float2* table(const vdwxc_ctx* h) { return h->d_table32; }
+  static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta32; }
+  static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm32; }
 };
 
 hipEvent_t take_event(vdwxc_ctx* h) {
@@ -394,26 +409,36 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   T2* B = static_cast<T2*>(h->d_B);
   dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
   stage_begin(h);
+  const size_t lds_theta = Prec<T>::theta_lds(h), lds_asm = Prec<T>::asm_lds(h);
   if (sig_from_grad)
-    hipLaunchKernelGGL((k_theta_zfwd<T, kPPT, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, n, sig, A,
+    hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, true>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A,
                        h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
   else
-    hipLaunchKernelGGL((k_theta_zfwd<T, kPPT, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, n, sig, A,
+    hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, false>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A,
                        h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
   stage_end(h, VDWXC_STAGE_THETA_ZFWD);
   enqueue_ypass<T>(h, h->M, -1, VDWXC_STAGE_Y_FWD);
   stage_begin(h);
-  hipLaunchKernelGGL((k_xcontract<T, kEPTX>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
-                     Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+  bool paired = false;
+  if constexpr (sizeof(T) == 4) {
+    if (h->ortho) {
+      paired = true;
+      hipLaunchKernelGGL((k_xcontract<T, kEPTX, 2>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
+                         Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+    }
+  }
+  if (!paired)
+    hipLaunchKernelGGL((k_xcontract<T, kEPTX, 1>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
+                       Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
   stage_end(h, VDWXC_STAGE_X_CONTRACT);
   enqueue_ypass<T>(h, h->M, +1, VDWXC_STAGE_Y_INV);
   stage_begin(h);
   if (sig_from_grad)
-    hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, n,
+    hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, true>), zgrid, dim3(Lz.nthr), lds_asm, h->stream, A, n,
                        sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile,
                        Lz.lstride);
   else
-    hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, n,
+    hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, false>), zgrid, dim3(Lz.nthr), lds_asm, h->stream, A, n,
                        sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile,
                        Lz.lstride);
   stage_end(h, VDWXC_STAGE_Z_ASSEMBLE);
@@ -561,15 +586,47 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   g.kmax = kmax;
   g.nk = nk;
   g.inv_dk = double(nk - 1) / kmax;
+  for (int i = 0; i < 3; ++i)
+    g.bn2[i] = g.bvec[3 * i] * g.bvec[3 * i] + g.bvec[3 * i + 1] * g.bvec[3 * i + 1] + g.bvec[3 * i + 2] * g.bvec[3 * i + 2];
+  {
+    bool ortho = true;
+    for (int i = 0; i < 3; ++i)
+      for (int j = i + 1; j < 3; ++j) {
+        const double d = cell[3 * i] * cell[3 * j] + cell[3 * i + 1] * cell[3 * j + 1] + cell[3 * i + 2] * cell[3 * j + 2];
+        const double ni = std::sqrt(cell[3 * i] * cell[3 * i] + cell[3 * i + 1] * cell[3 * i + 1] + cell[3 * i + 2] * cell[3 * i + 2]);
+        const double nj = std::sqrt(cell[3 * j] * cell[3 * j] + cell[3 * j + 1] * cell[3 * j + 1] + cell[3 * j + 2] * cell[3 * j + 2]);
+        if (std::fabs(d) > 1e-14 * ni * nj) ortho = false;
+      }
+    h->ortho = ortho;
+  }
   if (!(max_gnorm2(n, g.bvec) < kmax * kmax)) {
     release(h);
     return fail(nullptr, VDWXC_EINVAL, "grid reaches |G| >= kmax of the kernel table (grid too fine)");
   }
   bool ok = line_launch(0, h->n3, h->n2, 16, h->zl64) && line_launch(0, h->n3, h->n2, 8, h->zl32) &&
             line_launch(0, h->n2, h->n1, 16, h->yl64) && line_launch(0, h->n2, h->n1, 8, h->yl32) &&
-            xline_launch(3, h->n1, 16, h->xs64) && xline_launch(3, h->n1, 8, h->xs32);
-  if (precision == VDWXC_FP64) ok = ok && xline_launch(nq, h->n1, 16, h->xl64);
-  else ok = ok && xline_launch(nq, h->n1, 8, h->xl32);
+            xline_launch(3, h->n1, h->n1, 16, h->xs64) && xline_launch(3, h->n1, h->n1, 8, h->xs32);
+  if (precision == VDWXC_FP64) ok = ok && xline_launch(nq, h->n1, h->n1, 16, h->xl64);
+  else ok = ok && xline_launch(nq, h->n1, h->ortho ? h->n1 / 2 + 1 : h->n1, 8, h->xl32);
+  // the z passes keep three per-point values in LDS next to the lines: shrink the tile until
+  // they fit (the plain-field z passes use the same tile)
+  auto fit_state = [&](Launch& L, size_t cplx, size_t real) {
+    while (L.tile > 1) {
+      const size_t npts = size_t(L.tile) * h->n3;
+      const size_t need = L.lds + npts * 3 * real + ((npts + 15) & ~size_t(15)) + 4096;
+      if (need <= kMaxLds) break;
+      L.tile /= 2;
+      L.nthr = threads_for(long(L.tile) * h->n3, kEPT);
+      L.lds = size_t(L.tile) * L.lstride * cplx;
+    }
+  };
+  fit_state(h->zl64, 16, 8);
+  fit_state(h->zl32, 8, 4);
+  h->lds_theta64 = zstate_lds<double>(h->zl64, h->n3, 2);
+  h->lds_theta32 = zstate_lds<float>(h->zl32, h->n3, 2);
+  h->lds_asm64 = zstate_lds<double>(h->zl64, h->n3, 3);
+  h->lds_asm32 = zstate_lds<float>(h->zl32, h->n3, 3);
+  ok = ok && h->lds_asm64 <= kMaxLds && h->lds_asm32 <= kMaxLds;
   if (!ok) {
     release(h);
     return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
@@ -586,10 +643,24 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   natural_spline_moments(h->qmesh, mm);
   if ((e = upload(&h->d_q, h->qmesh.data(), nq)) != hipSuccess) return bail(e, "q-mesh upload");
   if ((e = upload(&h->d_mm, mm.data(), mm.size())) != hipSuccess) return bail(e, "spline upload");
-  if ((e = upload(&h->d_table64, table, tsz)) != hipSuccess) return bail(e, "table upload");
-  if (precision == VDWXC_FP32_MIXED) {
-    std::vector<float> t32(table, table + tsz);
-    if ((e = upload(&h->d_table32, t32.data(), tsz)) != hipSuccess) return bail(e, "table upload");
+  {
+    // per unordered pair (a <= b): (T_j, T_j+1) for j = 0..nk-1 (the last node repeated)
+    const size_t tn = size_t(kNumPairs) * nk;
+    std::vector<double2> t64(tn, double2{0.0, 0.0});
+    for (int a = 0; a < nq; ++a)
+      for (int b = a; b < nq; ++b)
+        for (int j = 0; j < nk; ++j) {
+          const int j1 = std::min(j + 1, nk - 1);
+          t64[size_t(pair_index(a, b)) * nk + j] = double2{table[(size_t(j) * nq + a) * nq + b],
+                                                           table[(size_t(j1) * nq + a) * nq + b]};
+        }
+    if (precision == VDWXC_FP64) {
+      if ((e = upload(&h->d_table64, t64.data(), tn)) != hipSuccess) return bail(e, "table upload");
+    } else {
+      std::vector<float2> t32(tn);
+      for (size_t i = 0; i < tn; ++i) t32[i] = float2{float(t64[i].x), float(t64[i].y)};
+      if ((e = upload(&h->d_table32, t32.data(), tn)) != hipSuccess) return bail(e, "table upload");
+    }
   }
   for (int a = 0; a < 3; ++a) {
     auto t64 = twiddles<double2, double>(n[a]);
@@ -613,14 +684,14 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     return bail(e, "pinned flag");
 
   // dynamic LDS above the default limit
-  set_lds_limit(k_theta_zfwd<double, kPPT, kEPT, false>, h->zl64.lds);
-  set_lds_limit(k_theta_zfwd<double, kPPT, kEPT, true>, h->zl64.lds);
-  set_lds_limit(k_theta_zfwd<float, kPPT, kEPT, false>, h->zl32.lds);
-  set_lds_limit(k_theta_zfwd<float, kPPT, kEPT, true>, h->zl32.lds);
-  set_lds_limit(k_zinv_assemble<double, kPPT, kEPT, false>, h->zl64.lds);
-  set_lds_limit(k_zinv_assemble<double, kPPT, kEPT, true>, h->zl64.lds);
-  set_lds_limit(k_zinv_assemble<float, kPPT, kEPT, false>, h->zl32.lds);
-  set_lds_limit(k_zinv_assemble<float, kPPT, kEPT, true>, h->zl32.lds);
+  set_lds_limit(k_theta_zfwd<double, kEPT, false>, h->lds_theta64);
+  set_lds_limit(k_theta_zfwd<double, kEPT, true>, h->lds_theta64);
+  set_lds_limit(k_theta_zfwd<float, kEPT, false>, h->lds_theta32);
+  set_lds_limit(k_theta_zfwd<float, kEPT, true>, h->lds_theta32);
+  set_lds_limit(k_zinv_assemble<double, kPPT, kEPT, false>, h->lds_asm64);
+  set_lds_limit(k_zinv_assemble<double, kPPT, kEPT, true>, h->lds_asm64);
+  set_lds_limit(k_zinv_assemble<float, kPPT, kEPT, false>, h->lds_asm32);
+  set_lds_limit(k_zinv_assemble<float, kPPT, kEPT, true>, h->lds_asm32);
   set_lds_limit(k_real_zfwd<double, kEPT, 0>, h->zl64.lds);
   set_lds_limit(k_real_zfwd<double, kEPT, 1>, h->zl64.lds);
   set_lds_limit(k_real_zfwd<float, kEPT, 1>, h->zl32.lds);
@@ -631,8 +702,9 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
   set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32.lds);
-  if (precision == VDWXC_FP64) set_lds_limit(k_xcontract<double, kEPTX>, h->xl64.lds);
-  else set_lds_limit(k_xcontract<float, kEPTX>, h->xl32.lds);
+  set_lds_limit(k_xcontract<double, kEPTX, 1>, h->xl64.lds);
+  set_lds_limit(k_xcontract<float, kEPTX, 1>, h->xl32.lds);
+  set_lds_limit(k_xcontract<float, kEPTX, 2>, h->xl32.lds);
   set_lds_limit(k_xspectral<double, kEPTX, 1, 3>, h->xs64.lds);
   set_lds_limit(k_xspectral<double, kEPTX, 3, 1>, h->xs64.lds);
   set_lds_limit(k_xspectral<float, kEPTX, 3, 1>, h->xs32.lds);
