@@ -57,6 +57,28 @@ def cpu_baseline(workload_name: str, n_cpu, g_cpu, w, kt):
     return rec, E, v
 
 
+def serving_measurement(kt, count, rate, precision):
+    """Poisson stream of `count` energy+potential requests (grids 48..160^3) through the
+    continuous-batching server: once with a 64 GB HBM budget, once capped at 1 GB so admission
+    queues.  Densities are generated on the device before the clock starts."""
+    import torch
+
+    from paper_1703_06999_amd import serving
+    print(f"[bench] serving: generating {count} requests", file=sys.stderr, flush=True)
+    reqs = serving.poisson_requests(count, rate, seed=0)
+    res = {"requests": count, "rate_per_s": rate, "grids": [48, 64, 96, 128, 160], "precision": precision}
+    for label, budget in (("budget_64GB", 64e9), ("budget_1GB", 1e9)):
+        for r in reqs:
+            r.admitted = r.finished = r.energy = r.v = None
+        srv = serving.Server(kt, slots=4, precision=precision, hbm_budget=budget)
+        summary = srv.run(reqs)
+        srv.close()
+        torch.cuda.empty_cache()
+        res[label] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summary.items()}
+        print(f"[bench] serving {label}: {res[label]}", file=sys.stderr, flush=True)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +87,9 @@ def main() -> int:
     ap.add_argument("--workload", default="slater_128")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=40.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not supported "
@@ -134,6 +159,10 @@ def main() -> int:
                         "v_maxnorm_rel_err_vs_oracle": float(np.max(np.abs(vv - v_ref)) / np.max(np.abs(v_ref))),
                         "v_density_weighted_l1": float(np.sum(nc * np.abs(vv - v_ref)) / np.sum(nc * np.abs(v_ref)))}
 
+    serve = None
+    if not args.no_serve:
+        serve = serving_measurement(kt, args.serve_requests, args.serve_rate, args.precision)
+
     out = {
         "metric": "grid pts/s for E_c^nl+v_c^nl (Nalpha=20) at stated rel. error; p50/p99 serve latency",
         "value": value,
@@ -154,6 +183,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "accuracy": accuracy,
         "stages": {k: {kk: round(vv, 4) for kk, vv in d.items()} for k, d in per_stage.items()},
+        "serving": serve,
     }
     print(json.dumps(out), flush=True)
     return 0

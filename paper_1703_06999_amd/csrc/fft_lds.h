@@ -213,7 +213,10 @@ __device__ __forceinline__ void run_stages(T2* buf, int n, int count, int& p, in
 template <int EPT, int DIR, typename T2>
 __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
                         const T2* __restrict__ tw, int tid, int nthr) {
-  const int n = plan.n;
+  int n = plan.n;
+  // keep the per-stage constants of this call from being hoisted into registers that stay live
+  // across a caller's loop around the transform
+  asm volatile("" : "+s"(n));
   int cnt[6] = {0, 0, 0, 0, 0, 0};   // radix 8, 4, 2, 3, 5, 7
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.radix[s];

@@ -114,6 +114,24 @@ __device__ __forceinline__ void split_pair(T2 zk, T2 zn, T2& xa, T2& xb) {
   xb = T2{half * (zk.y + zn.y), half * (zn.x - zk.x)};
 }
 
+// ---- twiddles staged in LDS ----------------------------------------------------------------------
+// Every axis (at most kMaxAxis points) keeps its twiddle table exp(-2 pi i t/n) in the first bytes
+// of the block's dynamic LDS, so the barrier-separated FFT stages never wait on global memory.
+constexpr int kMaxAxis = 2048;
+
+template <typename T2>
+__host__ __device__ constexpr size_t tw_lds_bytes(int n) {
+  return (size_t(n) * sizeof(T2) + 15) / 16 * 16;
+}
+
+template <typename T2>
+__device__ __forceinline__ const T2* stage_twiddles(unsigned char* smem_raw, const T2* __restrict__ tw, int n,
+                                                    int tid, int nthr) {
+  T2* t = reinterpret_cast<T2*>(smem_raw);
+  for (int i = tid; i < n; i += nthr) t[i] = tw[i];
+  return t;   // visible after the kernel's next barrier
+}
+
 // ---- XCD-aware block order ---------------------------------------------------------------------
 // The dispatcher hands block b to XCD b mod 8, and each XCD has its own L2.  Remapping the linear
 // block id so that consecutive logical tiles land on the same XCD lets the two blocks that write
@@ -202,13 +220,15 @@ __device__ __forceinline__ double point_sigma(const double* __restrict__ sig, si
 // evaluated once per point in FP64; theta_a = n p_a(q0) is formed in the path's precision T.
 
 template <typename T, int EPT, bool SIGMA_FROM_GRAD>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512)
 k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
              typename Cx<T>::type* __restrict__ A, int* __restrict__ flag,
              const double* __restrict__ qmesh, const double* __restrict__ mm,
              const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
   const int tid = threadIdx.x, nthr = blockDim.x;
   int tile, x;
   zpass_block(tile, x);
@@ -228,6 +248,7 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
   __syncthreads();
 
   bool bad = false;
+#pragma unroll 1
   for (int p = tid; p < npts; p += nthr) {
     const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
     int b = -1;
@@ -248,8 +269,10 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
   __syncthreads();
 
   const int npairs = (M + 1) >> 1;
+#pragma unroll 1
   for (int pr = 0; pr < npairs; ++pr) {
     const int fa = 2 * pr, fb = 2 * pr + 1;
+#pragma unroll 1
     for (int p = tid; p < npts; p += nthr) {
       const int yl = p / n3, z = p - yl * n3;
       const int b = st_b[p];
@@ -262,8 +285,9 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
       line[yl * lstride + z] = T2{ta, tb};
     }
     __syncthreads();
-    lds_fft<EPT, -1>(line, zp, ty, lstride, tw, tid, nthr);
+    lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
     const int nout = ty * g.h3;
+#pragma unroll 1
     for (int e = tid; e < nout; e += nthr) {
       const int yl = e % ty, kz = e / ty, y = y0 + yl;
       if (y < g.n2) {
@@ -284,12 +308,14 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
 // input), S = dE/dsigma (src) and g the gradient (aux, [3][N]).
 
 template <typename T, int EPT, int MODE>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512)
 k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int nf,
             typename Cx<T>::type* __restrict__ A, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   int tile, x;
@@ -298,8 +324,10 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
   const int n3 = g.n3;
   const size_t N = size_t(g.n1) * g.n2 * n3;
   const int npts = ty * n3;
+#pragma unroll 1
   for (int fa = 0; fa < nf; fa += 2) {
     const int fb = fa + 1;
+#pragma unroll 1
     for (int p = tid; p < npts; p += nthr) {
       const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
       double va = 0.0, vb = 0.0;
@@ -317,8 +345,9 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
       line[yl * lstride + z] = T2{T(va), T(vb)};
     }
     __syncthreads();
-    lds_fft<EPT, -1>(line, zp, ty, lstride, tw, tid, nthr);
+    lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
     const int nout = ty * g.h3;
+#pragma unroll 1
     for (int e = tid; e < nout; e += nthr) {
       const int yl = e % ty, kz = e / ty, y = y0 + yl;
       if (y < g.n2) {
@@ -342,7 +371,9 @@ __global__ void __launch_bounds__(1024)
 k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __restrict__ dst,
         const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan yp, int tx, int lstride) {
   using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n2);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n2, threadIdx.x, blockDim.x);
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nb = gridDim.x * gridDim.y * gridDim.z;
@@ -362,7 +393,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     }
   }
   __syncthreads();
-  lds_fft<EPT, DIR>(line, yp, tx, lstride, tw, tid, nthr);
+  lds_fft<EPT, DIR>(line, yp, tx, lstride, twl, tid, nthr);
   if (DIR < 0) {
     for (int e = tid; e < tot; e += nthr) {
       const int xl = e % tx, ky = e / tx;
@@ -417,8 +448,10 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
             double* __restrict__ partials, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
   using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
-  T2* line = reinterpret_cast<T2*>(smem);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n1);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n1, threadIdx.x, blockDim.x);
+  T2* line = reinterpret_cast<T2*>(smem);   // all M field lines of the column
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int ky = blockIdx.x, kz = blockIdx.y, M = g.M, n1 = g.n1;
   for (int e = tid; e < M * n1; e += nthr) {
@@ -427,81 +460,82 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   }
   __syncthreads();
   const int G = (nthr * EPT) / n1;   // lines per batched transform
-  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1>(line + l0 * n1, xp, min(G, M - l0), n1, tw, tid, nthr);
+  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1>(line + l0 * n1, xp, min(G, M - l0), n1, twl, tid, nthr);
 
-  const double wz = (kz == 0 || is_nyquist(kz, g.n3)) ? 1.0 : 2.0;
-  const double fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
-  const double g2yz = fy * fy * g.bn2[1] + fz * fz * g.bn2[2];
+  // this thread's k-points: slot s = tid; NPT = 2 pairs kx with -kx (orthogonal cells)
   const int nslots = NPT == 2 ? n1 / 2 + 1 : n1;
-  double esum = 0.0;
-  for (int s = tid; s < nslots; s += nthr) {
-    int kx[NPT];
-    bool valid[NPT];
-    kx[0] = s;
-    valid[0] = true;
-    double kn;
-    if (NPT == 2) {
-      kx[NPT - 1] = (n1 - s) % n1;
-      valid[NPT - 1] = (s != 0) && (2 * s != n1);
-      const double fx = double(s);
-      kn = sqrt(fx * fx * g.bn2[0] + g2yz);
-    } else {
-      kn = sqrt(gnorm2(g, s, ky, kz));
-    }
-    const bool inside = kn < g.kmax;
-    const double sc = kn * g.inv_dk;
-    int j = inside ? int(floor(sc)) : 0;
-    if (j > g.nk - 2) j = g.nk - 2;
-    const T w = T(inside ? sc - j : 0.0);
-    const T w0 = inside ? T(1) - w : T(0);
-    const T w1 = inside ? w : T(0);
-    T2 th[NPT][kMaxQ];
+  const bool has = tid < nslots;
+  int kx[NPT];
+  bool valid[NPT];
+  kx[0] = tid;
+  valid[0] = has;
+  if (NPT == 2) {
+    kx[NPT - 1] = (n1 - tid) % n1;
+    valid[NPT - 1] = has && tid != 0 && 2 * tid != n1;
+  }
+  T2 th[NPT][kMaxQ];
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) {
+  for (int q = 0; q < NPT; ++q)
 #pragma unroll
-      for (int a = 0; a < kMaxQ; ++a) th[q][a] = (a < M && valid[q]) ? line[a * n1 + kx[q]] : T2{T(0), T(0)};
-    }
-    const T2* tp = table2 + j;
-    T e[NPT];
+    for (int a = 0; a < kMaxQ; ++a) th[q][a] = (a < M && valid[q]) ? line[a * n1 + kx[q]] : T2{T(0), T(0)};
+
+  double kn;
+  if (NPT == 2) {
+    const double fx = double(tid), fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
+    kn = sqrt(fx * fx * g.bn2[0] + fy * fy * g.bn2[1] + fz * fz * g.bn2[2]);
+  } else {
+    kn = sqrt(gnorm2(g, has ? tid : 0, ky, kz));
+  }
+  const bool inside = kn < g.kmax;
+  const double sc = kn * g.inv_dk;
+  int j = inside ? int(floor(sc)) : 0;
+  if (j > g.nk - 2) j = g.nk - 2;
+  const T w = T(inside ? sc - j : 0.0);
+  const T w0 = inside ? T(1) - w : T(0);
+  const T w1 = inside ? w : T(0);
+  const T2* tp = table2 + j;
+  T e[NPT];
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) e[q] = T(0);
-    // one row a at a time: its M table entries are independent loads that can all be in flight
+  for (int q = 0; q < NPT; ++q) e[q] = T(0);
+  // one row a at a time: its M table entries are independent loads that can all be in flight
 #pragma unroll
-    for (int a = 0; a < kMaxQ; ++a) {
-      if (a < M) {
-        T2 row[kMaxQ];
+  for (int a = 0; a < kMaxQ; ++a) {
+    if (a < M && has) {
+      T2 row[kMaxQ];
 #pragma unroll
-        for (int b = 0; b < kMaxQ; ++b)
-          row[b] = b < M ? tp[size_t(a <= b ? pair_index(a, b) : pair_index(b, a)) * g.nk] : T2{T(0), T(0)};
-        T2 F[NPT];
+      for (int b = 0; b < kMaxQ; ++b)
+        row[b] = b < M ? tp[size_t(a <= b ? pair_index(a, b) : pair_index(b, a)) * g.nk] : T2{T(0), T(0)};
+      T2 F[NPT];
 #pragma unroll
-        for (int q = 0; q < NPT; ++q) F[q] = T2{T(0), T(0)};
+      for (int q = 0; q < NPT; ++q) F[q] = T2{T(0), T(0)};
 #pragma unroll
-        for (int b = 0; b < kMaxQ; ++b) {
-          const T phi = w0 * row[b].x + w1 * row[b].y;
-#pragma unroll
-          for (int q = 0; q < NPT; ++q) {
-            F[q].x += phi * th[q][b].x;
-            F[q].y += phi * th[q][b].y;
-          }
-        }
+      for (int b = 0; b < kMaxQ; ++b) {
+        const T phi = w0 * row[b].x + w1 * row[b].y;
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
-          e[q] += th[q][a].x * F[q].x + th[q][a].y * F[q].y;
-          if (valid[q]) line[a * n1 + kx[q]] = F[q];
+          F[q].x += phi * th[q][b].x;
+          F[q].y += phi * th[q][b].y;
         }
       }
-    }
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) esum += wz * double(e[q]);
+      for (int q = 0; q < NPT; ++q) {
+        e[q] += th[q][a].x * F[q].x + th[q][a].y * F[q].y;
+        if (valid[q]) line[a * n1 + kx[q]] = F[q];
+      }
+    }
   }
   __syncthreads();
-  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1>(line + l0 * n1, xp, min(G, M - l0), n1, tw, tid, nthr);
-  for (int e = tid; e < M * n1; e += nthr) {
-    const int f = e / n1, x = e - f * n1;
-    B[b_index(g, f, ky, kz, x)] = line[e];
+  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1>(line + l0 * n1, xp, min(G, M - l0), n1, twl, tid, nthr);
+  for (int e2 = tid; e2 < M * n1; e2 += nthr) {
+    const int f = e2 / n1, x = e2 - f * n1;
+    B[b_index(g, f, ky, kz, x)] = line[e2];
   }
+
   // block sum of the energy, fixed order: wave shuffles, then the waves in order
+  const double wz = (kz == 0 || is_nyquist(kz, g.n3)) ? 1.0 : 2.0;
+  double esum = 0.0;
+#pragma unroll
+  for (int q = 0; q < NPT; ++q) esum += wz * double(e[q]);
   for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
   __syncthreads();
   double* red = reinterpret_cast<double*>(smem);
@@ -522,7 +556,9 @@ __global__ void __launch_bounds__(512)
 k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
   using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n1);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n1, threadIdx.x, blockDim.x);
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int ky = blockIdx.x, kz = blockIdx.y, n1 = g.n1;
@@ -532,7 +568,7 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   }
   __syncthreads();
   const int G = (nthr * EPT) / n1;
-  for (int l0 = 0; l0 < NIN; l0 += G) lds_fft<EPT, -1>(line + l0 * n1, xp, min(G, NIN - l0), n1, tw, tid, nthr);
+  for (int l0 = 0; l0 < NIN; l0 += G) lds_fft<EPT, -1>(line + l0 * n1, xp, min(G, NIN - l0), n1, twl, tid, nthr);
   const bool nyq_yz = is_nyquist(ky, g.n2) || is_nyquist(kz, g.n3);
   const double fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
   for (int kx = tid; kx < n1; kx += nthr) {
@@ -562,7 +598,7 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
     }
   }
   __syncthreads();
-  for (int l0 = 0; l0 < NOUT; l0 += G) lds_fft<EPT, +1>(line + l0 * n1, xp, min(G, NOUT - l0), n1, tw, tid, nthr);
+  for (int l0 = 0; l0 < NOUT; l0 += G) lds_fft<EPT, +1>(line + l0 * n1, xp, min(G, NOUT - l0), n1, twl, tid, nthr);
   for (int e = tid; e < NOUT * n1; e += nthr) {
     const int f = e / n1, x = e - f * n1;
     B[b_index(g, f, ky, kz, x)] = line[e];
@@ -600,13 +636,15 @@ __device__ __forceinline__ void load_pair_line(const T2* __restrict__ A, const G
 // registers.
 
 template <typename T, int PPT, int EPT, bool SIGMA_FROM_GRAD>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512)
 k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __restrict__ nden,
                 const double* __restrict__ sig, double* __restrict__ dedn, double* __restrict__ dedsig,
                 const double* __restrict__ qmesh, const double* __restrict__ mm,
                 const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
   const int tid = threadIdx.x, nthr = blockDim.x;
   int tile, x;
   zpass_block(tile, x);
@@ -627,6 +665,7 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
   const SplineLds<T> S = load_spline_lds<T>(smem, off, qmesh, mm, M, tid, nthr);
   __syncthreads();
 
+#pragma unroll 1
   for (int p = tid; p < npts; p += nthr) {
     const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
     int b = -1;
@@ -645,11 +684,12 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
 #pragma unroll
   for (int c = 0; c < PPT; ++c) acc_n[c] = acc_s[c] = 0.0;
   const int npairs = (M + 1) >> 1;
+#pragma unroll 1
   for (int pr = 0; pr < npairs; ++pr) {
     const int fa = 2 * pr, fb = 2 * pr + 1 < M ? 2 * pr + 1 : -1;
     load_pair_line(A, g, fa, fb, x, y0, ty, line, lstride, tid, nthr);
     __syncthreads();
-    lds_fft<EPT, +1>(line, zp, ty, lstride, tw, tid, nthr);
+    lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
 #pragma unroll
     for (int c = 0; c < PPT; ++c) {
       const int p = tid + c * nthr;
@@ -692,11 +732,13 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
 // ---- pass 5 for plain real fields: out[f] = IFFT/N (COMBINE: out[0] -= IFFT/N) -------------
 
 template <typename T, int EPT, bool COMBINE>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512)
 k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restrict__ out,
             const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   int tile, x;
@@ -706,11 +748,13 @@ k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restri
   const size_t N = size_t(g.n1) * g.n2 * n3;
   const double invN = 1.0 / double(N);
   const int npts = ty * n3;
+#pragma unroll 1
   for (int fa = 0; fa < nf; fa += 2) {
     const int fb = fa + 1 < nf ? fa + 1 : -1;
     load_pair_line(A, g, fa, fb, x, y0, ty, line, lstride, tid, nthr);
     __syncthreads();
-    lds_fft<EPT, +1>(line, zp, ty, lstride, tw, tid, nthr);
+    lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
+#pragma unroll 1
     for (int p = tid; p < npts; p += nthr) {
       const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
       if (y < g.n2) {

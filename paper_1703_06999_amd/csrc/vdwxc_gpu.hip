@@ -23,11 +23,12 @@ using namespace vdwxc;
 
 namespace {
 
-constexpr int kPPT = 4;          // grid points per thread in the z passes
-constexpr int kEPT = 4;          // FFT elements per thread in the z and y passes
+constexpr int kPPT = 8;          // grid points per thread in the z passes
+constexpr int kEPT = 8;          // FFT elements per thread in the z and y passes
 constexpr int kEPTX = 8;         // FFT elements per thread in the x passes
-constexpr int kMaxThreads = 1024;  // z and y passes
-constexpr int kMaxThreadsX = 256;  // x passes (large register footprint of the contraction)
+constexpr int kMaxThreadsZ = 512;  // z passes
+constexpr int kMaxThreadsY = 1024; // y passes
+constexpr int kMaxThreadsX = 512;  // x passes: one thread per contraction slot
 constexpr int kLineTile = 16;    // lines per block in the z and y passes
 constexpr size_t kMaxLds = 160 * 1024;
 
@@ -202,22 +203,22 @@ std::vector<T2> twiddles(int n) {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-// block size with >= `items / ept` threads, a multiple of 64, at most kMaxThreads
-int threads_for(long items, int ept) {
+// block size with >= `items / ept` threads, a multiple of 64, at most `maxt`
+int threads_for(long items, int ept, int maxt) {
   const long t = (items + ept - 1) / ept;
-  return int(std::min<long>(kMaxThreads, std::max<long>(64, round_up(int(std::min<long>(t, 1 << 20)), 64))));
+  return int(std::min<long>(maxt, std::max<long>(64, round_up(int(std::min<long>(t, 1 << 20)), 64))));
 }
 
-bool line_launch(int nlines_max, int n, int other, size_t cplx_bytes, Launch& L) {
-  // TILE lines of length n in one block (TILE <= min(16, other)), padded stride n + 1
+// TILE lines of length n in one block (TILE <= min(16, other)), padded stride n + 1; the LDS
+// size includes the twiddle table of the axis
+bool line_launch(int maxt, int n, int other, size_t cplx_bytes, Launch& L) {
   int tile = std::min(kLineTile, std::max(1, other));
-  while (tile > 1 && long(tile) * n > long(kMaxThreads) * kEPT) tile /= 2;
-  if (long(tile) * n > long(kMaxThreads) * kEPT) return false;
-  (void)nlines_max;
+  while (tile > 1 && long(tile) * n > long(maxt) * kEPT) tile /= 2;
+  if (long(tile) * n > long(maxt) * kEPT || n > kMaxAxis) return false;
   L.tile = tile;
-  L.nthr = threads_for(long(tile) * n, kEPT);
+  L.nthr = threads_for(long(tile) * n, kEPT, maxt);
   L.lstride = n + 1;
-  L.lds = size_t(tile) * (n + 1) * cplx_bytes;
+  L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) + size_t(tile) * (n + 1) * cplx_bytes;
   return L.lds + 4096 <= kMaxLds;
 }
 
@@ -227,9 +228,10 @@ bool xline_launch(int nlines, int n, int slots, size_t cplx_bytes, Launch& L) {
   // thread per contraction slot up to kMaxThreadsX
   L.tile = nlines;
   L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(slots, 64)));
-  if (n > L.nthr * kEPTX) return false;
+  if (n > L.nthr * kEPTX || n > kMaxAxis) return false;
   L.lstride = n;
-  L.lds = std::max<size_t>(size_t(nlines) * n * cplx_bytes, 16 * sizeof(double));
+  L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) +
+          std::max<size_t>(size_t(nlines) * n * cplx_bytes, 16 * sizeof(double));
   return L.lds <= kMaxLds;
 }
 
@@ -603,11 +605,15 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     release(h);
     return fail(nullptr, VDWXC_EINVAL, "grid reaches |G| >= kmax of the kernel table (grid too fine)");
   }
-  bool ok = line_launch(0, h->n3, h->n2, 16, h->zl64) && line_launch(0, h->n3, h->n2, 8, h->zl32) &&
-            line_launch(0, h->n2, h->n1, 16, h->yl64) && line_launch(0, h->n2, h->n1, 8, h->yl32) &&
+  bool ok = line_launch(kMaxThreadsZ, h->n3, h->n2, 16, h->zl64) && line_launch(kMaxThreadsZ, h->n3, h->n2, 8, h->zl32) &&
+            line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64) && line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32) &&
             xline_launch(3, h->n1, h->n1, 16, h->xs64) && xline_launch(3, h->n1, h->n1, 8, h->xs32);
-  if (precision == VDWXC_FP64) ok = ok && xline_launch(nq, h->n1, h->n1, 16, h->xl64);
-  else ok = ok && xline_launch(nq, h->n1, h->ortho ? h->n1 / 2 + 1 : h->n1, 8, h->xl32);
+  {
+    // contraction pass: one thread per slot (k-point, or kx/-kx pair in FP32 orthogonal cells)
+    const int slots = (precision == VDWXC_FP32_MIXED && h->ortho) ? h->n1 / 2 + 1 : h->n1;
+    Launch& L = precision == VDWXC_FP64 ? h->xl64 : h->xl32;
+    ok = ok && slots <= kMaxThreadsX && xline_launch(nq, h->n1, slots, precision == VDWXC_FP64 ? 16 : 8, L);
+  }
   // the z passes keep three per-point values in LDS next to the lines: shrink the tile until
   // they fit (the plain-field z passes use the same tile)
   auto fit_state = [&](Launch& L, size_t cplx, size_t real) {
@@ -616,8 +622,8 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
       const size_t need = L.lds + npts * 3 * real + ((npts + 15) & ~size_t(15)) + 4096;
       if (need <= kMaxLds) break;
       L.tile /= 2;
-      L.nthr = threads_for(long(L.tile) * h->n3, kEPT);
-      L.lds = size_t(L.tile) * L.lstride * cplx;
+      L.nthr = threads_for(long(L.tile) * h->n3, kEPT, kMaxThreadsZ);
+      L.lds = ((size_t(h->n3) * cplx + 15) & ~size_t(15)) + size_t(L.tile) * L.lstride * cplx;
     }
   };
   fit_state(h->zl64, 16, 8);

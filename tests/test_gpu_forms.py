@@ -1,0 +1,172 @@
+"""The differentiation and serving forms on the GPU.
+
+* VdwxcEnergy (forward E, hand-written backward v dV) against central finite differences of the
+  FP64 forward on 64 random points of the 192^3 / 28 Angstrom / 600-blob workload (h = 1e-5), in
+  FP64 and FP32, and against the oracle's potential in spectral-gradient mode.
+* The continuous-batching server: every request's (E, v) bitwise equal alone and in the mix,
+  admission under a reduced HBM budget, and agreement with the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import vdwdf
+from paper_1703_06999_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+KT = inputs.synthetic_kernel_table()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_06999_amd import vdwxc
+    vdwxc.lib()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def c3(dev):
+    w = inputs.workload("slater_192")
+    n, _ = w.density(device="cuda")
+    return w, n
+
+
+def _fd_points(n, count=64, seed=5):
+    rng = np.random.default_rng(inputs.SEED_BASE + 400 + seed)
+    cand = torch.nonzero(n.reshape(-1) >= 1e-3).reshape(-1).cpu().numpy()
+    return rng.choice(cand, size=count, replace=False)
+
+
+def test_autograd_finite_differences_192(dev, c3):
+    from paper_1703_06999_amd import vdwxc
+    from paper_1703_06999_amd.autograd import vdwxc_energy
+    w, n = c3
+    say("[autograd FD] 192^3 fp64 + fp32 backward")
+    f64 = vdwxc.Functional(w.grid, w.cell, precision="fp64", table=KT)
+    f32 = vdwxc.Functional(w.grid, w.cell, precision="fp32", table=KT)
+    grads = {}
+    for name, f in (("fp64", f64), ("fp32", f32)):
+        x = n.clone().requires_grad_(True)
+        E = vdwxc_energy(x, f)
+        E.backward()
+        grads[name] = x.grad.reshape(-1)
+    h = 1e-5
+    pts = _fd_points(n)
+    flat = n.reshape(-1)
+    gmax = float(torch.max(torch.abs(grads["fp64"])))
+    worst64 = worst32 = 0.0
+    for j in pts:
+        xp = flat.clone()
+        xm = flat.clone()
+        xp[j] += h
+        xm[j] -= h
+        Ep, _ = f64.potential(xp.reshape(n.shape), None)
+        Em, _ = f64.potential(xm.reshape(n.shape), None)
+        fd = (Ep - Em) / (2 * h)
+        g64 = float(grads["fp64"][j])
+        g32 = float(grads["fp32"][j])
+        worst64 = max(worst64, abs(g64 - fd) / abs(fd))
+        worst32 = max(worst32, abs(g32 - fd) / (1e-3 * abs(fd) + 1e-4 * gmax))
+        assert abs(g64 - fd) <= 1e-5 * abs(fd), (j, g64, fd)
+        assert abs(g32 - fd) <= 1e-3 * abs(fd) + 1e-4 * gmax, (j, g32, fd)
+    say(f"    fp64 worst FD rel error {worst64:.2e}; fp32 worst error / tolerance {worst32:.2e}")
+
+
+@pytest.mark.timeout(900)
+def test_autograd_backward_matches_oracle_potential_192(dev, c3):
+    from paper_1703_06999_amd import vdwxc
+    from paper_1703_06999_amd.autograd import vdwxc_energy
+    w, n = c3
+    say("[autograd vs oracle] 192^3 spectral gradient")
+    nc = n.cpu().numpy()
+    E_ref, v_ref, _, _ = vdwdf.potential(nc, w.cell, KT, grad=None)
+    dV = float(np.linalg.det(w.cell)) / nc.size
+    for prec, tol_e, tol_v in (("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-4)):
+        f = vdwxc.Functional(w.grid, w.cell, precision=prec, table=KT)
+        x = n.clone().requires_grad_(True)
+        E = vdwxc_energy(x, f)
+        E.backward()
+        g = x.grad.cpu().numpy() / dV
+        e_err = abs(float(E) - E_ref) / abs(E_ref)
+        v_err = np.max(np.abs(g - v_ref)) / np.max(np.abs(v_ref))
+        say(f"    {prec}: E rel {e_err:.2e}, v max-norm rel {v_err:.2e}")
+        assert e_err <= tol_e and v_err <= tol_v
+
+
+def _small_requests(count, rate, seed, grids=(16, 24, 30, 32)):
+    from paper_1703_06999_amd import serving
+    rng = np.random.default_rng(inputs.SEED_BASE + 500 + seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    reqs = []
+    for i in range(count):
+        g = int(rng.choice(grids))
+        L = g * 0.3
+        n, grad = inputs.small_slater((g, g, g), L, int(rng.integers(2, 6)), seed=1000 * seed + i, floor=1e-5,
+                                      device="cuda")
+        reqs.append(serving.Request(i, (g, g, g), inputs.cubic_cell(L), n, grad, arrival=float(t[i])))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def _alone(req, precision):
+    from paper_1703_06999_amd import vdwxc
+    f = vdwxc.Functional(req.grid, req.cell, precision=precision, table=KT)
+    E, v = f.potential(req.n, req.grad)
+    f.close()
+    return E, v
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_serving_alone_equals_mix_bitwise(dev, precision):
+    from paper_1703_06999_amd import serving
+    say(f"[serving burst] {precision}")
+    reqs = _small_requests(24, rate=2000.0, seed=1)
+    srv = serving.Server(KT, slots=4, precision=precision)
+    summary = srv.run(reqs)
+    srv.close()
+    say(f"    {summary}")
+    assert summary["requests"] == len(reqs)
+    assert summary["max_concurrent"] >= 2     # the burst really overlapped on the device
+    for r in reqs:
+        E, v = _alone(r, precision)
+        assert float(r.energy.item()) == E and torch.equal(r.v, v), r.rid
+
+
+def test_serving_admission_under_small_budget(dev):
+    from paper_1703_06999_amd import serving, vdwxc
+    say("[serving small budget]")
+    reqs = _small_requests(12, rate=5000.0, seed=2, grids=(24, 32))
+    budget = 1.5 * vdwxc.workspace_bytes((32, 32, 32), "fp32", KT.nq)
+    srv = serving.Server(KT, slots=4, precision="fp32", hbm_budget=budget)
+    summary = srv.run(reqs)
+    srv.close()
+    say(f"    {summary}")
+    assert summary["requests"] == len(reqs)
+    assert summary["resident_bytes"] == 0.0
+    assert summary["max_concurrent"] <= 2
+    for r in reqs:
+        E, v = _alone(r, "fp32")
+        assert float(r.energy.item()) == E and torch.equal(r.v, v)
+
+
+def test_serving_results_match_oracle(dev):
+    from paper_1703_06999_amd import serving
+    say("[serving vs oracle]")
+    reqs = _small_requests(6, rate=1000.0, seed=3, grids=(16, 24))
+    srv = serving.Server(KT, slots=3, precision="fp64")
+    srv.run(reqs)
+    srv.close()
+    for r in reqs:
+        E_ref, v_ref, _, _ = vdwdf.potential(r.n.cpu().numpy(), r.cell, KT, grad=r.grad.cpu().numpy())
+        assert float(r.energy.item()) == pytest.approx(E_ref, rel=1e-10)
+        v = r.v.cpu().numpy()
+        assert np.max(np.abs(v - v_ref)) <= 1e-10 * np.max(np.abs(v_ref))
