@@ -90,6 +90,9 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=40.0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after the timed steps, run one plain device copy of this many MiB (a "
+                         "kernel of known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not supported "
@@ -123,6 +126,14 @@ def main() -> int:
     t1 = time.perf_counter()
     stages = f.read_timing()
     f.enable_timing(False)
+    if args.copy_calibration_mb:
+        nel = args.copy_calibration_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = w.npoints * args.steps / elapsed

@@ -89,10 +89,11 @@ def saturation(x, a=SATURATION_A):
     t = x / a
     S = np.zeros_like(t)
     dS = np.zeros_like(t)          # dS/dx = (1/a) sum_{m=1}^{12} t^{m-1}
-    for m in range(1, SATURATION_TERMS + 1):
-        S = S + t ** m / m
-        dS = dS + t ** (m - 1)
-    e = np.exp(-S)
+    with np.errstate(over="ignore"):   # huge t only occurs on the saturated branch below
+        for m in range(1, SATURATION_TERMS + 1):
+            S = S + t ** m / m
+            dS = dS + t ** (m - 1)
+        e = np.exp(-S)
     h = a * (1.0 - e)
     saturated = t >= 2.0           # exp(-S) == 0 exactly in FP64 there
     hprime = np.where(saturated, 0.0, e * np.where(saturated, 0.0, dS))

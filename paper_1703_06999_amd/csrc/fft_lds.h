@@ -1,6 +1,6 @@
 // Batched 1D FFTs of lines held in LDS, for gfx950 (64-wide wavefronts).
 //
-// A workgroup owns `nlines` lines of length n, stored in LDS at buf[l*lstride + i].  Each radix-R
+// A workgroup owns `nlines` lines of length n, stored in LDS at buf[l*lstride + lidx(i)].  Each radix-R
 // stage is a Stockham autosort step: butterfly i (0 <= i < n/R) of a line reads the R elements
 // i + r*n/R, applies twiddles exp(-+2 pi i r k/(pR)) with k = i mod p (p = product of the radices
 // already done), runs an R-point DFT and writes element (i - k)*R + k + r*p.  Output is in natural
@@ -14,6 +14,16 @@
 namespace vdwxc {
 
 constexpr int kMaxStages = 16;
+
+// Position of element i of a line in LDS: one padding slot after every 2^kLdsPadShift elements,
+// so the strided writes of the early Stockham stages (stride R, then groups of p) spread over the
+// LDS banks.  A line of n elements occupies lds_span(n) slots.
+#ifndef VDWXC_LDS_PAD_SHIFT
+#define VDWXC_LDS_PAD_SHIFT 3
+#endif
+constexpr int kLdsPadShift = VDWXC_LDS_PAD_SHIFT;
+__host__ __device__ constexpr int lidx(int i) { return i + (i >> kLdsPadShift); }
+__host__ __device__ constexpr int lds_span(int n) { return n <= 0 ? 0 : lidx(n - 1) + 1; }
 
 // Radix schedule of one transform length: radices 8, 4, 2, 3, 5, 7.
 struct AxisPlan {
@@ -162,7 +172,7 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
   const int total = nb * nlines;
   const int twstep = n / (p * R);
   T2 v[MAXB][R];
-  int dst[MAXB];
+  int dst[MAXB], lbase[MAXB];
 #pragma unroll
   for (int c = 0; c < MAXB; ++c) {
     const int b = tid + c * nthr;
@@ -171,9 +181,9 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
       const int l = b / nb;
       const int i = b - l * nb;
       const int k = i % p;
-      const T2* src = buf + l * lstride + i;
+      const T2* src = buf + l * lstride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[c][r] = src[r * nb];
+      for (int r = 0; r < R; ++r) v[c][r] = src[lidx(i + r * nb)];
       if (p > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -183,7 +193,8 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
         }
       }
       SmallDft<R, DIR, T2>::run(v[c]);
-      dst[c] = l * lstride + (i - k) * R + k;
+      dst[c] = (i - k) * R + k;
+      lbase[c] = l * lstride;
     }
   }
   __syncthreads();
@@ -191,7 +202,7 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
   for (int c = 0; c < MAXB; ++c) {
     if (dst[c] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[dst[c] + r * p] = v[c][r];
+      for (int r = 0; r < R; ++r) buf[lbase[c] + lidx(dst[c] + r * p)] = v[c][r];
     }
   }
   __syncthreads();

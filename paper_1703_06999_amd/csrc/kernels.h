@@ -282,7 +282,7 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
         ta = nv * S.p(fa, b, t);
         if (fb < M) tb = nv * S.p(fb, b, t);
       }
-      line[yl * lstride + z] = T2{ta, tb};
+      line[yl * lstride + lidx(z)] = T2{ta, tb};
     }
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
@@ -291,8 +291,8 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
     for (int e = tid; e < nout; e += nthr) {
       const int yl = e % ty, kz = e / ty, y = y0 + yl;
       if (y < g.n2) {
-        const T2 zk = line[yl * lstride + kz];
-        const T2 zn = line[yl * lstride + (kz == 0 ? 0 : n3 - kz)];
+        const T2 zk = line[yl * lstride + lidx(kz)];
+        const T2 zn = line[yl * lstride + lidx(kz == 0 ? 0 : n3 - kz)];
         T2 xa, xb;
         split_pair(zk, zn, xa, xb);
         A[a_index(g, fa, kz, x, y)] = xa;
@@ -342,7 +342,7 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
           if (fb < nf) vb = s2 * aux[size_t(fb) * N + idx];
         }
       }
-      line[yl * lstride + z] = T2{T(va), T(vb)};
+      line[yl * lstride + lidx(z)] = T2{T(va), T(vb)};
     }
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
@@ -351,8 +351,8 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
     for (int e = tid; e < nout; e += nthr) {
       const int yl = e % ty, kz = e / ty, y = y0 + yl;
       if (y < g.n2) {
-        const T2 zk = line[yl * lstride + kz];
-        const T2 zn = line[yl * lstride + (kz == 0 ? 0 : n3 - kz)];
+        const T2 zk = line[yl * lstride + lidx(kz)];
+        const T2 zn = line[yl * lstride + lidx(kz == 0 ? 0 : n3 - kz)];
         T2 xa, xb;
         split_pair(zk, zn, xa, xb);
         A[a_index(g, fa, kz, x, y)] = xa;
@@ -384,12 +384,12 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     const size_t base = a_index(g, f, kz, x0, 0);
     for (int e = tid; e < tot; e += nthr) {
       const int xl = e / n2, y = e - xl * n2;
-      line[xl * lstride + y] = (x0 + xl < g.n1) ? src[base + e] : T2{T(0), T(0)};
+      line[xl * lstride + lidx(y)] = (x0 + xl < g.n1) ? src[base + e] : T2{T(0), T(0)};
     }
   } else {
     for (int e = tid; e < tot; e += nthr) {
       const int xl = e % tx, ky = e / tx;
-      line[xl * lstride + ky] = (x0 + xl < g.n1) ? src[b_index(g, f, ky, kz, x0 + xl)] : T2{T(0), T(0)};
+      line[xl * lstride + lidx(ky)] = (x0 + xl < g.n1) ? src[b_index(g, f, ky, kz, x0 + xl)] : T2{T(0), T(0)};
     }
   }
   __syncthreads();
@@ -397,13 +397,13 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
   if (DIR < 0) {
     for (int e = tid; e < tot; e += nthr) {
       const int xl = e % tx, ky = e / tx;
-      if (x0 + xl < g.n1) dst[b_index(g, f, ky, kz, x0 + xl)] = line[xl * lstride + ky];
+      if (x0 + xl < g.n1) dst[b_index(g, f, ky, kz, x0 + xl)] = line[xl * lstride + lidx(ky)];
     }
   } else {
     const size_t base = a_index(g, f, kz, x0, 0);
     for (int e = tid; e < tot; e += nthr) {
       const int xl = e / n2, y = e - xl * n2;
-      if (x0 + xl < g.n1) dst[base + e] = line[xl * lstride + y];
+      if (x0 + xl < g.n1) dst[base + e] = line[xl * lstride + lidx(y)];
     }
   }
 }
@@ -454,13 +454,14 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   T2* line = reinterpret_cast<T2*>(smem);   // all M field lines of the column
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int ky = blockIdx.x, kz = blockIdx.y, M = g.M, n1 = g.n1;
+  const int ls = lds_span(n1);
   for (int e = tid; e < M * n1; e += nthr) {
     const int f = e / n1, x = e - f * n1;
-    line[e] = B[b_index(g, f, ky, kz, x)];
+    line[f * ls + lidx(x)] = B[b_index(g, f, ky, kz, x)];
   }
   __syncthreads();
   const int G = (nthr * EPT) / n1;   // lines per batched transform
-  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1>(line + l0 * n1, xp, min(G, M - l0), n1, twl, tid, nthr);
+  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
 
   // this thread's k-points: slot s = tid; NPT = 2 pairs kx with -kx (orthogonal cells)
   const int nslots = NPT == 2 ? n1 / 2 + 1 : n1;
@@ -477,7 +478,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
 #pragma unroll
   for (int q = 0; q < NPT; ++q)
 #pragma unroll
-    for (int a = 0; a < kMaxQ; ++a) th[q][a] = (a < M && valid[q]) ? line[a * n1 + kx[q]] : T2{T(0), T(0)};
+    for (int a = 0; a < kMaxQ; ++a) th[q][a] = (a < M && valid[q]) ? line[a * ls + lidx(kx[q])] : T2{T(0), T(0)};
 
   double kn;
   if (NPT == 2) {
@@ -520,15 +521,15 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
 #pragma unroll
       for (int q = 0; q < NPT; ++q) {
         e[q] += th[q][a].x * F[q].x + th[q][a].y * F[q].y;
-        if (valid[q]) line[a * n1 + kx[q]] = F[q];
+        if (valid[q]) line[a * ls + lidx(kx[q])] = F[q];
       }
     }
   }
   __syncthreads();
-  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1>(line + l0 * n1, xp, min(G, M - l0), n1, twl, tid, nthr);
+  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
   for (int e2 = tid; e2 < M * n1; e2 += nthr) {
     const int f = e2 / n1, x = e2 - f * n1;
-    B[b_index(g, f, ky, kz, x)] = line[e2];
+    B[b_index(g, f, ky, kz, x)] = line[f * ls + lidx(x)];
   }
 
   // block sum of the energy, fixed order: wave shuffles, then the waves in order
@@ -562,13 +563,14 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int ky = blockIdx.x, kz = blockIdx.y, n1 = g.n1;
+  const int ls = lds_span(n1);
   for (int e = tid; e < NIN * n1; e += nthr) {
     const int f = e / n1, x = e - f * n1;
-    line[e] = B[b_index(g, f, ky, kz, x)];
+    line[f * ls + lidx(x)] = B[b_index(g, f, ky, kz, x)];
   }
   __syncthreads();
   const int G = (nthr * EPT) / n1;
-  for (int l0 = 0; l0 < NIN; l0 += G) lds_fft<EPT, -1>(line + l0 * n1, xp, min(G, NIN - l0), n1, twl, tid, nthr);
+  for (int l0 = 0; l0 < NIN; l0 += G) lds_fft<EPT, -1>(line + l0 * ls, xp, min(G, NIN - l0), ls, twl, tid, nthr);
   const bool nyq_yz = is_nyquist(ky, g.n2) || is_nyquist(kz, g.n3);
   const double fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
   for (int kx = tid; kx < n1; kx += nthr) {
@@ -579,12 +581,12 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
     for (int c = 0; c < 3; ++c) G[c] = fx * g.bvec[c] + fy * g.bvec[3 + c] + fz * g.bvec[6 + c];
     T2 in[NIN];
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) in[f] = line[f * n1 + kx];
+    for (int f = 0; f < NIN; ++f) in[f] = line[f * ls + lidx(kx)];
     if (NIN == 1) {
 #pragma unroll
       for (int c = 0; c < NOUT; ++c) {   // i G_c X
         const T gc = zero ? T(0) : T(G[c]);
-        line[c * n1 + kx] = T2{-gc * in[0].y, gc * in[0].x};
+        line[c * ls + lidx(kx)] = T2{-gc * in[0].y, gc * in[0].x};
       }
     } else {
       T2 acc = T2{T(0), T(0)};
@@ -594,19 +596,31 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
         acc.x -= gc * in[c].y;
         acc.y += gc * in[c].x;
       }
-      line[kx] = acc;
+      line[lidx(kx)] = acc;
     }
   }
   __syncthreads();
-  for (int l0 = 0; l0 < NOUT; l0 += G) lds_fft<EPT, +1>(line + l0 * n1, xp, min(G, NOUT - l0), n1, twl, tid, nthr);
+  for (int l0 = 0; l0 < NOUT; l0 += G) lds_fft<EPT, +1>(line + l0 * ls, xp, min(G, NOUT - l0), ls, twl, tid, nthr);
   for (int e = tid; e < NOUT * n1; e += nthr) {
     const int f = e / n1, x = e - f * n1;
-    B[b_index(g, f, ky, kz, x)] = line[e];
+    B[b_index(g, f, ky, kz, x)] = line[f * ls + lidx(x)];
   }
 }
 
 // Rebuild the full complex z-line Z = X_a + i X_b of a field pair from their half spectra (the
 // imaginary parts of the k = 0 and Nyquist terms are dropped, as a complex-to-real transform does).
+template <typename T2>
+__device__ __forceinline__ void store_pair_values(T2 xa, T2 xb, int kz, int yl, int n3, T2* line, int lstride) {
+  using T = decltype(line[0].x);
+  const bool edge = (kz == 0) || is_nyquist(kz, n3);
+  if (edge) {
+    xa.y = T(0);
+    xb.y = T(0);
+  }
+  line[yl * lstride + lidx(kz)] = T2{xa.x - xb.y, xa.y + xb.x};
+  if (!edge) line[yl * lstride + lidx(n3 - kz)] = T2{xa.x + xb.y, xb.x - xa.y};
+}
+
 template <typename T2>
 __device__ __forceinline__ void load_pair_line(const T2* __restrict__ A, const Geometry& g, int fa, int fb,
                                                int x, int y0, int ty, T2* line, int lstride, int tid, int nthr) {
@@ -619,15 +633,41 @@ __device__ __forceinline__ void load_pair_line(const T2* __restrict__ A, const G
       xa = A[a_index(g, fa, kz, x, y)];
       if (fb >= 0) xb = A[a_index(g, fb, kz, x, y)];
     }
-    const bool edge = (kz == 0) || is_nyquist(kz, n3);
-    if (edge) {
-      xa.y = T(0);
-      xb.y = T(0);
-    }
-    line[yl * lstride + kz] = T2{xa.x - xb.y, xa.y + xb.x};
-    if (!edge) line[yl * lstride + (n3 - kz)] = T2{xa.x + xb.y, xb.x - xa.y};
+    store_pair_values(xa, xb, kz, yl, n3, line, lstride);
   }
 }
+
+// The half spectra of one field pair for a z-pass tile, held in registers so that the next pair's
+// loads are in flight while the current pair is transformed.  PF >= ceil(ty*h3 / nthr).
+template <typename T2, int PF>
+struct PairPrefetch {
+  T2 a[PF], b[PF];
+  __device__ __forceinline__ void issue(const T2* __restrict__ A, const Geometry& g, int fa, int fb, int x, int y0,
+                                        int ty, int tid, int nthr) {
+    using T = decltype(a[0].x);
+    const int tot = ty * g.h3;
+#pragma unroll
+    for (int c = 0; c < PF; ++c) {
+      const int e = tid + c * nthr;
+      a[c] = b[c] = T2{T(0), T(0)};
+      if (e < tot) {
+        const int yl = e % ty, kz = e / ty, y = y0 + yl;
+        if (y < g.n2) {
+          a[c] = A[a_index(g, fa, kz, x, y)];
+          if (fb >= 0) b[c] = A[a_index(g, fb, kz, x, y)];
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void store(const Geometry& g, int ty, T2* line, int lstride, int tid, int nthr) const {
+    const int tot = ty * g.h3;
+#pragma unroll
+    for (int c = 0; c < PF; ++c) {
+      const int e = tid + c * nthr;
+      if (e < tot) store_pair_values(a[c], b[c], e / ty, e % ty, g.n3, line, lstride);
+    }
+  }
+};
 
 // ---- pass 5: inverse z FFT + assembly of dE/dn, dE/dsigma (eqs. dedn, dedsigma) -------------
 // dE/dn = sum_a F_a [p_a + n p_a' dq0/dn],  dE/dsigma = sum_a F_a n p_a' dq0/dsigma, with F_a(r)
@@ -684,11 +724,14 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
 #pragma unroll
   for (int c = 0; c < PPT; ++c) acc_n[c] = acc_s[c] = 0.0;
   const int npairs = (M + 1) >> 1;
+  PairPrefetch<T2, EPT / 2 + 1> pf;
+  pf.issue(A, g, 0, M > 1 ? 1 : -1, x, y0, ty, tid, nthr);
 #pragma unroll 1
   for (int pr = 0; pr < npairs; ++pr) {
     const int fa = 2 * pr, fb = 2 * pr + 1 < M ? 2 * pr + 1 : -1;
-    load_pair_line(A, g, fa, fb, x, y0, ty, line, lstride, tid, nthr);
+    pf.store(g, ty, line, lstride, tid, nthr);
     __syncthreads();
+    if (pr + 1 < npairs) pf.issue(A, g, fa + 2, fa + 3 < M ? fa + 3 : -1, x, y0, ty, tid, nthr);
     lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
 #pragma unroll
     for (int c = 0; c < PPT; ++c) {
@@ -697,7 +740,7 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
         const int b = st_b[p];
         if (b != 255) {
           const int yl = p / n3, z = p - yl * n3;
-          const T2 F = line[yl * lstride + z];
+          const T2 F = line[yl * lstride + lidx(z)];
           const T t = st_t[p], an = st_an[p], as = st_as[p];
           const T pa = S.p(fa, b, t), dpa = S.dp(fa, b, t);
           T vn = F.x * (pa + an * dpa);
@@ -759,7 +802,7 @@ k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restri
       const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
       if (y < g.n2) {
         const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-        const T2 v = line[yl * lstride + z];
+        const T2 v = line[yl * lstride + lidx(z)];
         if (COMBINE) {
           out[idx] -= double(v.x) * invN;
         } else {

@@ -25,7 +25,10 @@ namespace {
 
 constexpr int kPPT = 8;          // grid points per thread in the z passes
 constexpr int kEPT = 8;          // FFT elements per thread in the z and y passes
-constexpr int kEPTX = 8;         // FFT elements per thread in the x passes
+#ifndef VDWXC_EPTX
+#define VDWXC_EPTX 8
+#endif
+constexpr int kEPTX = VDWXC_EPTX;  // FFT elements per thread in the x passes
 constexpr int kMaxThreadsZ = 512;  // z passes
 constexpr int kMaxThreadsY = 1024; // y passes
 constexpr int kMaxThreadsX = 512;  // x passes: one thread per contraction slot
@@ -217,8 +220,8 @@ bool line_launch(int maxt, int n, int other, size_t cplx_bytes, Launch& L) {
   if (long(tile) * n > long(maxt) * kEPT || n > kMaxAxis) return false;
   L.tile = tile;
   L.nthr = threads_for(long(tile) * n, kEPT, maxt);
-  L.lstride = n + 1;
-  L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) + size_t(tile) * (n + 1) * cplx_bytes;
+  L.lstride = lds_span(n) | 1;   // odd: the transposed tile accesses hit distinct banks
+  L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) + size_t(tile) * L.lstride * cplx_bytes;
   return L.lds + 4096 <= kMaxLds;
 }
 
@@ -229,9 +232,9 @@ bool xline_launch(int nlines, int n, int slots, size_t cplx_bytes, Launch& L) {
   L.tile = nlines;
   L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(slots, 64)));
   if (n > L.nthr * kEPTX || n > kMaxAxis) return false;
-  L.lstride = n;
+  L.lstride = lds_span(n);
   L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) +
-          std::max<size_t>(size_t(nlines) * n * cplx_bytes, 16 * sizeof(double));
+          std::max<size_t>(size_t(nlines) * L.lstride * cplx_bytes, 16 * sizeof(double));
   return L.lds <= kMaxLds;
 }
 

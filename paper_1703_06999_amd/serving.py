@@ -66,6 +66,7 @@ class Server:
         self.queue: collections.deque = collections.deque()
         self.done: list[Request] = []
         self.max_concurrent = 0
+        self.peak_resident = 0.0
 
     # ---- memory accounting -----------------------------------------------------------------
     def _cost(self, grid) -> float:
@@ -95,6 +96,7 @@ class Server:
                                  table=self.table, stream=slot.stream)
         slot.handles[key] = h
         self.resident += need
+        self.peak_resident = max(self.peak_resident, self.resident)
         return h
 
     # ---- scheduling --------------------------------------------------------------------------
@@ -168,7 +170,7 @@ class Server:
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "max_concurrent": self.max_concurrent,
-            "resident_bytes": self.resident,
+            "peak_resident_bytes": self.peak_resident,
         }
 
     def close(self):

@@ -253,3 +253,60 @@ def test_translation_invariance_192(dev):
     E2, v2 = f.potential(torch.roll(n, sh, (0, 1, 2)).contiguous(), torch.roll(g, sh, (1, 2, 3)).contiguous())
     assert E2 == pytest.approx(E, rel=1e-12)
     assert torch.max(torch.abs(v2 - torch.roll(v, sh, (0, 1, 2)))) <= 1e-11 * torch.max(torch.abs(v))
+
+
+@pytest.fixture(scope="module")
+def nano512(dev):
+    w = inputs.workload("nanoparticle_512")
+    n, g = w.density(device="cuda")
+    return w, n, g
+
+
+@pytest.mark.timeout(600)
+def test_nanoparticle_512_fp32_against_fp64(dev, nano512):
+    """512^3 / 48 Angstrom / 9696 blobs, in the launch configuration bench.py times: the FP32 form
+    against the FP64 path (which the oracle pins at smaller sizes), at the FP32 tolerances."""
+    say("[nanoparticle 512^3] fp32 vs fp64")
+    w, n, g = nano512
+    f64 = functional(w.grid, w.cell, "fp64")
+    E64, v64 = f64.potential(n, g)
+    f64.close()
+    f32 = functional(w.grid, w.cell, "fp32")
+    E32, v32 = f32.potential(n, g)
+    f32.close()
+    say(f"    E64 {E64:.12e}  E32 {E32:.12e}")
+    assert abs(E32 - E64) <= 1e-5 * abs(E64)
+    scale = float(torch.max(torch.abs(v64)))
+    err = float(torch.max(torch.abs(v32 - v64))) / scale
+    wl1 = float(torch.sum(n * torch.abs(v32 - v64)) / torch.sum(n * torch.abs(v64)))
+    say(f"    v max-norm rel {err:.2e}, density-weighted L1 {wl1:.2e}")
+    assert err <= 1e-4 and wl1 <= 1e-5
+    assert bool(torch.all(torch.isfinite(v32)))
+
+
+@pytest.mark.timeout(600)
+def test_nanoparticle_512_translation(dev, nano512):
+    say("[nanoparticle 512^3] translation, fp32")
+    w, n, g = nano512
+    f = functional(w.grid, w.cell, "fp32")
+    E, v = f.potential(n, g)
+    sh = (17, -5, 33)
+    E2, v2 = f.potential(torch.roll(n, sh, (0, 1, 2)).contiguous(), torch.roll(g, sh, (1, 2, 3)).contiguous())
+    f.close()
+    assert abs(E2 - E) <= 1e-6 * abs(E)
+    assert float(torch.max(torch.abs(v2 - torch.roll(v, sh, (0, 1, 2))))) <= 1e-5 * float(torch.max(torch.abs(v)))
+
+
+def test_uniform_gas_512_fp32(dev):
+    """Uniform density on the 512^3 / 48 Angstrom grid: only k = 0 survives (closed form)."""
+    say("[uniform gas 512^3] fp32")
+    w = inputs.workload("nanoparticle_512")
+    n0 = 0.01
+    n1 = np.full((1, 1, 1), n0)
+    E1, dn1, ds1 = vdwdf.energy_and_partials(n1, np.zeros((1, 1, 1)), w.cell, KT)
+    f = functional(w.grid, w.cell, "fp32")
+    n = torch.full(w.grid, n0, dtype=torch.float64, device=dev)
+    E, dn, ds = f.calculate(n, torch.zeros_like(n))
+    f.close()
+    assert E == pytest.approx(E1, rel=1e-5)
+    assert float(torch.max(torch.abs(dn - float(dn1[0, 0, 0])))) <= 1e-5 * abs(float(dn1[0, 0, 0]))
