@@ -22,6 +22,32 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 M = 20
+def kernel_source_hash() -> str:
+    from paper_1703_06999_amd.profiling import source_hash
+    return source_hash()
+
+
+def profiled_traffic(workload: str, precision: str, stage: str):
+    """HBM bytes per launch of `stage` from the committed rocprofv3 counter summary
+    (profiles/traffic_<workload>_<precision>.md: FETCH_SIZE and WRITE_SIZE scaled by a plain
+    streaming kernel of known size), or None if there is none or the kernel sources changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    src_hash, rows = None, {}
+    for line in open(path):
+        if line.startswith("source_sha256:"):
+            src_hash = line.split(":", 1)[1].strip()
+        elif line.startswith("| `") and "|" in line[3:]:
+            cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            try:
+                rows[cells[0]] = float(cells[-1])
+            except ValueError:
+                pass
+    if src_hash != kernel_source_hash() or stage not in rows:
+        return None
+    return rows[stage]
 
 
 def stage_bytes(stage: str, grid, precision: str, m: int = M) -> float:
@@ -127,11 +153,12 @@ def main() -> int:
     stages = f.read_timing()
     f.enable_timing(False)
     if args.copy_calibration_mb:
+        # one streaming elementwise kernel (negation) reading and writing N bytes each
         nel = args.copy_calibration_mb * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
     elapsed = t1 - t0
@@ -148,7 +175,8 @@ def main() -> int:
     avg_s = stages[dom][0] / stages[dom][1] * 1e-3
     achieved = stage_bytes(dom, w.grid, args.precision) / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic(args.workload, args.precision, dom),
                 "algorithmic_bytes_per_launch": stage_bytes(dom, w.grid, args.precision),
                 "avg_launch_ms": round(avg_s * 1e3, 4)}
 

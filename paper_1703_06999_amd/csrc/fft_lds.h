@@ -22,8 +22,28 @@ constexpr int kMaxStages = 16;
 #define VDWXC_LDS_PAD_SHIFT 3
 #endif
 constexpr int kLdsPadShift = VDWXC_LDS_PAD_SHIFT;
-__host__ __device__ constexpr int lidx(int i) { return i + (i >> kLdsPadShift); }
-__host__ __device__ constexpr int lds_span(int n) { return n <= 0 ? 0 : lidx(n - 1) + 1; }
+constexpr int kNoPad = 31;
+// kSwizzle: no padding; instead the low five index bits are XORed with bits 3..7 (a permutation of
+// every aligned group of 32 elements, so lines take a multiple of 32 slots).  The Stockham stages
+// read at unit stride and write at stride R p; the XOR spreads both over distinct banks without
+// the extra LDS of padding.
+constexpr int kSwizzle = 32;
+template <int PS = kLdsPadShift>
+__host__ __device__ constexpr int lidx(int i) {
+  if constexpr (PS == kSwizzle) {
+    return i ^ ((i >> 3) & 31);
+  } else {
+    return i + (i >> PS);
+  }
+}
+template <int PS = kLdsPadShift>
+__host__ __device__ constexpr int lds_span(int n) {
+  if constexpr (PS == kSwizzle) {
+    return (n + 31) & ~31;
+  } else {
+    return n <= 0 ? 0 : lidx<PS>(n - 1) + 1;
+  }
+}
 
 // Radix schedule of one transform length: radices 8, 4, 2, 3, 5, 7.
 struct AxisPlan {
@@ -165,7 +185,7 @@ template <int DIR, typename T2> struct SmallDft<7, DIR, T2> : OddDft<7, DIR, T2>
 
 // ---- one Stockham stage on LDS lines ---------------------------------------------------------
 
-template <int R, int MAXB, int DIR, typename T2>
+template <int R, int MAXB, int DIR, int PS, typename T2>
 __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstride, int p,
                                           const T2* __restrict__ tw, int tid, int nthr) {
   const int nb = n / R;
@@ -183,7 +203,7 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
       const int k = i % p;
       const T2* src = buf + l * lstride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[c][r] = src[lidx(i + r * nb)];
+      for (int r = 0; r < R; ++r) v[c][r] = src[lidx<PS>(i + r * nb)];
       if (p > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -202,7 +222,7 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
   for (int c = 0; c < MAXB; ++c) {
     if (dst[c] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lbase[c] + lidx(dst[c] + r * p)] = v[c][r];
+      for (int r = 0; r < R; ++r) buf[lbase[c] + lidx<PS>(dst[c] + r * p)] = v[c][r];
     }
   }
   __syncthreads();
@@ -212,16 +232,16 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
 // must have synchronised after filling the lines; the lines are complete on return.  The plan
 // lists its radices grouped (all 8s, then 4, 2, 3s, 5s, 7s), so each radix runs in its own loop
 // and the register allocation of one stage kind does not inflate the others.
-template <int R, int EPT, int DIR, typename T2>
+template <int R, int EPT, int DIR, int PS, typename T2>
 __device__ __forceinline__ void run_stages(T2* buf, int n, int count, int& p, int nlines, int lstride,
                                            const T2* __restrict__ tw, int tid, int nthr) {
   for (int s = 0; s < count; ++s) {
-    fft_stage<R, (EPT + R - 1) / R, DIR>(buf, n, nlines, lstride, p, tw, tid, nthr);
+    fft_stage<R, (EPT + R - 1) / R, DIR, PS>(buf, n, nlines, lstride, p, tw, tid, nthr);
     p *= R;
   }
 }
 
-template <int EPT, int DIR, typename T2>
+template <int EPT, int DIR, int PS = kLdsPadShift, typename T2>
 __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
                         const T2* __restrict__ tw, int tid, int nthr) {
   int n = plan.n;
@@ -234,12 +254,12 @@ __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
     cnt[R == 8 ? 0 : R == 4 ? 1 : R == 2 ? 2 : R == 3 ? 3 : R == 5 ? 4 : 5] += 1;
   }
   int p = 1;
-  run_stages<8, EPT, DIR>(buf, n, cnt[0], p, nlines, lstride, tw, tid, nthr);
-  run_stages<4, EPT, DIR>(buf, n, cnt[1], p, nlines, lstride, tw, tid, nthr);
-  run_stages<2, EPT, DIR>(buf, n, cnt[2], p, nlines, lstride, tw, tid, nthr);
-  run_stages<3, EPT, DIR>(buf, n, cnt[3], p, nlines, lstride, tw, tid, nthr);
-  run_stages<5, EPT, DIR>(buf, n, cnt[4], p, nlines, lstride, tw, tid, nthr);
-  run_stages<7, EPT, DIR>(buf, n, cnt[5], p, nlines, lstride, tw, tid, nthr);
+  run_stages<8, EPT, DIR, PS>(buf, n, cnt[0], p, nlines, lstride, tw, tid, nthr);
+  run_stages<4, EPT, DIR, PS>(buf, n, cnt[1], p, nlines, lstride, tw, tid, nthr);
+  run_stages<2, EPT, DIR, PS>(buf, n, cnt[2], p, nlines, lstride, tw, tid, nthr);
+  run_stages<3, EPT, DIR, PS>(buf, n, cnt[3], p, nlines, lstride, tw, tid, nthr);
+  run_stages<5, EPT, DIR, PS>(buf, n, cnt[4], p, nlines, lstride, tw, tid, nthr);
+  run_stages<7, EPT, DIR, PS>(buf, n, cnt[5], p, nlines, lstride, tw, tid, nthr);
 }
 
 }  // namespace vdwxc

@@ -114,6 +114,30 @@ __device__ __forceinline__ void split_pair(T2 zk, T2 zn, T2& xa, T2& xb) {
   xb = T2{half * (zk.y + zn.y), half * (zn.x - zk.x)};
 }
 
+// ---- strided gathers with several loads in flight -------------------------------------------
+// Thread tid handles the elements e = tid, tid + nthr, ... of [0, tot).  Each group of U of them
+// is loaded first (get returns the raw loaded values, with no arithmetic that would have to wait
+// for them) and consumed after (put), so a thread keeps U independent global loads in flight
+// instead of waiting on each in turn.
+template <int U, typename Get, typename Put>
+__device__ __forceinline__ void gather_strided(int tid, int nthr, int tot, Get get, Put put) {
+  using V = decltype(get(0));
+#pragma unroll 1
+  for (int e0 = tid; e0 < tot; e0 += U * nthr) {
+    V r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < tot) r[u] = get(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < tot) put(e, r[u]);
+    }
+  }
+}
+
 // ---- twiddles staged in LDS ----------------------------------------------------------------------
 // Every axis (at most kMaxAxis points) keeps its twiddle table exp(-2 pi i t/n) in the first bytes
 // of the block's dynamic LDS, so the barrier-separated FFT stages never wait on global memory.
@@ -128,7 +152,7 @@ template <typename T2>
 __device__ __forceinline__ const T2* stage_twiddles(unsigned char* smem_raw, const T2* __restrict__ tw, int n,
                                                     int tid, int nthr) {
   T2* t = reinterpret_cast<T2*>(smem_raw);
-  for (int i = tid; i < n; i += nthr) t[i] = tw[i];
+  gather_strided<4>(tid, nthr, n, [&](int i) { return tw[i]; }, [&](int i, T2 v) { t[i] = v; });
   return t;   // visible after the kernel's next barrier
 }
 
@@ -206,12 +230,23 @@ constexpr size_t spline_lds_bytes() {
   return kMaxQ * sizeof(double) + (kMaxQ * kMaxQ + 2 * kMaxQ) * sizeof(T);
 }
 
-__device__ __forceinline__ double point_sigma(const double* __restrict__ sig, size_t idx, size_t N, bool from_grad) {
-  if (from_grad) {
-    const double gx = sig[idx], gy = sig[N + idx], gz = sig[2 * N + idx];
-    return gx * gx + gy * gy + gz * gz;
-  }
-  return sig[idx];
+// raw inputs of one point: n and either sigma (s[0]) or the three gradient components
+struct PointIn {
+  double n, s[3];
+};
+
+__device__ __forceinline__ PointIn point_load(const double* __restrict__ nden, const double* __restrict__ sig,
+                                              size_t idx, size_t N, bool from_grad) {
+  PointIn r;
+  r.n = nden[idx];
+  r.s[0] = sig[idx];
+  r.s[1] = from_grad ? sig[N + idx] : 0.0;
+  r.s[2] = from_grad ? sig[2 * N + idx] : 0.0;
+  return r;
+}
+
+__device__ __forceinline__ double point_sigma(const PointIn& r, bool from_grad) {
+  return from_grad ? r.s[0] * r.s[0] + r.s[1] * r.s[1] + r.s[2] * r.s[2] : r.s[0];
 }
 
 // ---- pass 1: q0 + splines + forward z FFT (theta fields) ------------------------------------
@@ -248,23 +283,28 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
   __syncthreads();
 
   bool bad = false;
-#pragma unroll 1
-  for (int p = tid; p < npts; p += nthr) {
-    const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
-    int b = -1;
-    double t = 0.0, nv = 0.0;
-    if (y < g.n2) {
-      const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-      nv = nden[idx];
-      const double sv = point_sigma(sig, idx, N, SIGMA_FROM_GRAD);
-      bad |= !(nv == nv) || !(sv == sv);
-      double d1, d2;
-      q0_state(nv, sv, g.zab, S.q, M, b, t, d1, d2);
-    }
-    st_b[p] = b < 0 ? 255 : (unsigned char)b;
-    st_t[p] = T(t);
-    st_n[p] = T(nv);
-  }
+  gather_strided<4>(
+      tid, nthr, npts,
+      [&](int p) {
+        const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+        PointIn r{0.0, {0.0, 0.0, 0.0}};
+        if (y < g.n2) r = point_load(nden, sig, (size_t(x) * g.n2 + y) * n3 + z, N, SIGMA_FROM_GRAD);
+        return r;
+      },
+      [&](int p, const PointIn& r) {
+        const int y = y0 + p / n3;
+        int b = -1;
+        double t = 0.0;
+        if (y < g.n2) {
+          const double sv = point_sigma(r, SIGMA_FROM_GRAD);
+          bad |= !(r.n == r.n) || !(sv == sv);
+          double d1, d2;
+          q0_state(r.n, sv, g.zab, S.q, M, b, t, d1, d2);
+        }
+        st_b[p] = b < 0 ? 255 : (unsigned char)b;
+        st_t[p] = T(t);
+        st_n[p] = T(r.n);
+      });
   if (bad) *flag = 1;
   __syncthreads();
 
@@ -282,7 +322,7 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
         ta = nv * S.p(fa, b, t);
         if (fb < M) tb = nv * S.p(fb, b, t);
       }
-      line[yl * lstride + lidx(z)] = T2{ta, tb};
+      line[yl * lstride + lidx<>(z)] = T2{ta, tb};
     }
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
@@ -291,8 +331,8 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
     for (int e = tid; e < nout; e += nthr) {
       const int yl = e % ty, kz = e / ty, y = y0 + yl;
       if (y < g.n2) {
-        const T2 zk = line[yl * lstride + lidx(kz)];
-        const T2 zn = line[yl * lstride + lidx(kz == 0 ? 0 : n3 - kz)];
+        const T2 zk = line[yl * lstride + lidx<>(kz)];
+        const T2 zn = line[yl * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
         T2 xa, xb;
         split_pair(zk, zn, xa, xb);
         A[a_index(g, fa, kz, x, y)] = xa;
@@ -327,23 +367,28 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
 #pragma unroll 1
   for (int fa = 0; fa < nf; fa += 2) {
     const int fb = fa + 1;
-#pragma unroll 1
-    for (int p = tid; p < npts; p += nthr) {
-      const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
-      double va = 0.0, vb = 0.0;
-      if (y < g.n2) {
-        const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-        if (MODE == 0) {
-          va = src[size_t(fa) * N + idx];
-          if (fb < nf) vb = src[size_t(fb) * N + idx];
-        } else {
-          const double s2 = 2.0 * src[idx];
-          va = s2 * aux[size_t(fa) * N + idx];
-          if (fb < nf) vb = s2 * aux[size_t(fb) * N + idx];
-        }
-      }
-      line[yl * lstride + lidx(z)] = T2{T(va), T(vb)};
-    }
+    struct Raw {
+      double a, b, s;
+    };
+    gather_strided<4>(
+        tid, nthr, npts,
+        [&](int p) {
+          const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+          Raw r{0.0, 0.0, 0.0};
+          if (y < g.n2) {
+            const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
+            const double* f = MODE == 0 ? src : aux;
+            r.a = f[size_t(fa) * N + idx];
+            if (fb < nf) r.b = f[size_t(fb) * N + idx];
+            if (MODE == 1) r.s = src[idx];
+          }
+          return r;
+        },
+        [&](int p, const Raw& r) {
+          const int yl = p / n3, z = p - yl * n3;
+          const double s2 = MODE == 0 ? 1.0 : 2.0 * r.s;
+          line[yl * lstride + lidx<>(z)] = T2{T(s2 * r.a), T(s2 * r.b)};
+        });
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
     const int nout = ty * g.h3;
@@ -351,8 +396,8 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
     for (int e = tid; e < nout; e += nthr) {
       const int yl = e % ty, kz = e / ty, y = y0 + yl;
       if (y < g.n2) {
-        const T2 zk = line[yl * lstride + lidx(kz)];
-        const T2 zn = line[yl * lstride + lidx(kz == 0 ? 0 : n3 - kz)];
+        const T2 zk = line[yl * lstride + lidx<>(kz)];
+        const T2 zn = line[yl * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
         T2 xa, xb;
         split_pair(zk, zn, xa, xb);
         A[a_index(g, fa, kz, x, y)] = xa;
@@ -382,28 +427,33 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
   const int n2 = g.n2, tot = tx * n2;
   if (DIR < 0) {
     const size_t base = a_index(g, f, kz, x0, 0);
-    for (int e = tid; e < tot; e += nthr) {
-      const int xl = e / n2, y = e - xl * n2;
-      line[xl * lstride + lidx(y)] = (x0 + xl < g.n1) ? src[base + e] : T2{T(0), T(0)};
-    }
+    gather_strided<8>(
+        tid, nthr, tot, [&](int e) { return (x0 + e / n2 < g.n1) ? src[base + e] : T2{T(0), T(0)}; },
+        [&](int e, T2 v) {
+          const int xl = e / n2, y = e - xl * n2;
+          line[xl * lstride + lidx<>(y)] = v;
+        });
   } else {
-    for (int e = tid; e < tot; e += nthr) {
-      const int xl = e % tx, ky = e / tx;
-      line[xl * lstride + lidx(ky)] = (x0 + xl < g.n1) ? src[b_index(g, f, ky, kz, x0 + xl)] : T2{T(0), T(0)};
-    }
+    gather_strided<8>(
+        tid, nthr, tot,
+        [&](int e) {
+          const int xl = e % tx, ky = e / tx;
+          return (x0 + xl < g.n1) ? src[b_index(g, f, ky, kz, x0 + xl)] : T2{T(0), T(0)};
+        },
+        [&](int e, T2 v) { line[(e % tx) * lstride + lidx<>(e / tx)] = v; });
   }
   __syncthreads();
   lds_fft<EPT, DIR>(line, yp, tx, lstride, twl, tid, nthr);
   if (DIR < 0) {
     for (int e = tid; e < tot; e += nthr) {
       const int xl = e % tx, ky = e / tx;
-      if (x0 + xl < g.n1) dst[b_index(g, f, ky, kz, x0 + xl)] = line[xl * lstride + lidx(ky)];
+      if (x0 + xl < g.n1) dst[b_index(g, f, ky, kz, x0 + xl)] = line[xl * lstride + lidx<>(ky)];
     }
   } else {
     const size_t base = a_index(g, f, kz, x0, 0);
     for (int e = tid; e < tot; e += nthr) {
       const int xl = e / n2, y = e - xl * n2;
-      if (x0 + xl < g.n1) dst[base + e] = line[xl * lstride + lidx(y)];
+      if (x0 + xl < g.n1) dst[base + e] = line[xl * lstride + lidx<>(y)];
     }
   }
 }
@@ -442,26 +492,27 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * kMaxQ - a * (a - 1) / 2 + (b - a); }
 constexpr int kNumPairs = kMaxQ * (kMaxQ + 1) / 2;
 
-template <typename T, int EPT, int NPT>
+// PS: LDS layout of the lines (kNoPad or kSwizzle: no padding).  Without padding and with the twiddles read
+// from global memory, the 20 FP32 lines of a 512-point axis take exactly 80 KB, so two blocks
+// share a CU and one block's HBM loads overlap the other's transforms and contraction.
+template <typename T, int EPT, int NPT, int PS>
 __global__ void __launch_bounds__(512)
 k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ table2,
             double* __restrict__ partials, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
   using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n1);
-  const T2* twl = stage_twiddles(smem_raw, tw, g.n1, threadIdx.x, blockDim.x);
+  extern __shared__ __align__(16) unsigned char smem[];
+  const T2* twl = tw;                       // twiddles from global memory (L1/L2 resident)
   T2* line = reinterpret_cast<T2*>(smem);   // all M field lines of the column
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int ky = blockIdx.x, kz = blockIdx.y, M = g.M, n1 = g.n1;
-  const int ls = lds_span(n1);
-  for (int e = tid; e < M * n1; e += nthr) {
-    const int f = e / n1, x = e - f * n1;
-    line[f * ls + lidx(x)] = B[b_index(g, f, ky, kz, x)];
-  }
+  const int ls = lds_span<PS>(n1);
+  gather_strided<16>(
+      tid, nthr, M * n1, [&](int e) { return B[b_index(g, e / n1, ky, kz, e % n1)]; },
+      [&](int e, T2 v) { line[(e / n1) * ls + lidx<PS>(e % n1)] = v; });
   __syncthreads();
   const int G = (nthr * EPT) / n1;   // lines per batched transform
-  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
+  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1, PS>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
 
   // this thread's k-points: slot s = tid; NPT = 2 pairs kx with -kx (orthogonal cells)
   const int nslots = NPT == 2 ? n1 / 2 + 1 : n1;
@@ -478,7 +529,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
 #pragma unroll
   for (int q = 0; q < NPT; ++q)
 #pragma unroll
-    for (int a = 0; a < kMaxQ; ++a) th[q][a] = (a < M && valid[q]) ? line[a * ls + lidx(kx[q])] : T2{T(0), T(0)};
+    for (int a = 0; a < kMaxQ; ++a) th[q][a] = (a < M && valid[q]) ? line[a * ls + lidx<PS>(kx[q])] : T2{T(0), T(0)};
 
   double kn;
   if (NPT == 2) {
@@ -521,15 +572,15 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
 #pragma unroll
       for (int q = 0; q < NPT; ++q) {
         e[q] += th[q][a].x * F[q].x + th[q][a].y * F[q].y;
-        if (valid[q]) line[a * ls + lidx(kx[q])] = F[q];
+        if (valid[q]) line[a * ls + lidx<PS>(kx[q])] = F[q];
       }
     }
   }
   __syncthreads();
-  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
+  for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1, PS>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
   for (int e2 = tid; e2 < M * n1; e2 += nthr) {
     const int f = e2 / n1, x = e2 - f * n1;
-    B[b_index(g, f, ky, kz, x)] = line[f * ls + lidx(x)];
+    B[b_index(g, f, ky, kz, x)] = line[f * ls + lidx<PS>(x)];
   }
 
   // block sum of the energy, fixed order: wave shuffles, then the waves in order
@@ -563,11 +614,10 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int ky = blockIdx.x, kz = blockIdx.y, n1 = g.n1;
-  const int ls = lds_span(n1);
-  for (int e = tid; e < NIN * n1; e += nthr) {
-    const int f = e / n1, x = e - f * n1;
-    line[f * ls + lidx(x)] = B[b_index(g, f, ky, kz, x)];
-  }
+  const int ls = lds_span<>(n1);
+  gather_strided<8>(
+      tid, nthr, NIN * n1, [&](int e) { return B[b_index(g, e / n1, ky, kz, e % n1)]; },
+      [&](int e, T2 v) { line[(e / n1) * ls + lidx<>(e % n1)] = v; });
   __syncthreads();
   const int G = (nthr * EPT) / n1;
   for (int l0 = 0; l0 < NIN; l0 += G) lds_fft<EPT, -1>(line + l0 * ls, xp, min(G, NIN - l0), ls, twl, tid, nthr);
@@ -581,12 +631,12 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
     for (int c = 0; c < 3; ++c) G[c] = fx * g.bvec[c] + fy * g.bvec[3 + c] + fz * g.bvec[6 + c];
     T2 in[NIN];
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) in[f] = line[f * ls + lidx(kx)];
+    for (int f = 0; f < NIN; ++f) in[f] = line[f * ls + lidx<>(kx)];
     if (NIN == 1) {
 #pragma unroll
       for (int c = 0; c < NOUT; ++c) {   // i G_c X
         const T gc = zero ? T(0) : T(G[c]);
-        line[c * ls + lidx(kx)] = T2{-gc * in[0].y, gc * in[0].x};
+        line[c * ls + lidx<>(kx)] = T2{-gc * in[0].y, gc * in[0].x};
       }
     } else {
       T2 acc = T2{T(0), T(0)};
@@ -596,14 +646,14 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
         acc.x -= gc * in[c].y;
         acc.y += gc * in[c].x;
       }
-      line[lidx(kx)] = acc;
+      line[lidx<>(kx)] = acc;
     }
   }
   __syncthreads();
   for (int l0 = 0; l0 < NOUT; l0 += G) lds_fft<EPT, +1>(line + l0 * ls, xp, min(G, NOUT - l0), ls, twl, tid, nthr);
   for (int e = tid; e < NOUT * n1; e += nthr) {
     const int f = e / n1, x = e - f * n1;
-    B[b_index(g, f, ky, kz, x)] = line[f * ls + lidx(x)];
+    B[b_index(g, f, ky, kz, x)] = line[f * ls + lidx<>(x)];
   }
 }
 
@@ -617,8 +667,8 @@ __device__ __forceinline__ void store_pair_values(T2 xa, T2 xb, int kz, int yl, 
     xa.y = T(0);
     xb.y = T(0);
   }
-  line[yl * lstride + lidx(kz)] = T2{xa.x - xb.y, xa.y + xb.x};
-  if (!edge) line[yl * lstride + lidx(n3 - kz)] = T2{xa.x + xb.y, xb.x - xa.y};
+  line[yl * lstride + lidx<>(kz)] = T2{xa.x - xb.y, xa.y + xb.x};
+  if (!edge) line[yl * lstride + lidx<>(n3 - kz)] = T2{xa.x + xb.y, xb.x - xa.y};
 }
 
 template <typename T2>
@@ -626,15 +676,21 @@ __device__ __forceinline__ void load_pair_line(const T2* __restrict__ A, const G
                                                int x, int y0, int ty, T2* line, int lstride, int tid, int nthr) {
   using T = decltype(line[0].x);
   const int n3 = g.n3, tot = ty * g.h3;
-  for (int e = tid; e < tot; e += nthr) {
-    const int yl = e % ty, kz = e / ty, y = y0 + yl;
-    T2 xa = T2{T(0), T(0)}, xb = T2{T(0), T(0)};
-    if (y < g.n2) {
-      xa = A[a_index(g, fa, kz, x, y)];
-      if (fb >= 0) xb = A[a_index(g, fb, kz, x, y)];
-    }
-    store_pair_values(xa, xb, kz, yl, n3, line, lstride);
-  }
+  struct Pair {
+    T2 a, b;
+  };
+  gather_strided<8>(
+      tid, nthr, tot,
+      [&](int e) {
+        const int yl = e % ty, kz = e / ty, y = y0 + yl;
+        Pair r{T2{T(0), T(0)}, T2{T(0), T(0)}};
+        if (y < g.n2) {
+          r.a = A[a_index(g, fa, kz, x, y)];
+          if (fb >= 0) r.b = A[a_index(g, fb, kz, x, y)];
+        }
+        return r;
+      },
+      [&](int e, const Pair& r) { store_pair_values(r.a, r.b, e / ty, e % ty, n3, line, lstride); });
 }
 
 // The half spectra of one field pair for a z-pass tile, held in registers so that the next pair's
@@ -705,20 +761,23 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
   const SplineLds<T> S = load_spline_lds<T>(smem, off, qmesh, mm, M, tid, nthr);
   __syncthreads();
 
-#pragma unroll 1
-  for (int p = tid; p < npts; p += nthr) {
-    const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
-    int b = -1;
-    double t = 0.0, an = 0.0, as = 0.0;
-    if (y < g.n2) {
-      const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-      q0_state(nden[idx], point_sigma(sig, idx, N, SIGMA_FROM_GRAD), g.zab, S.q, M, b, t, an, as);
-    }
-    st_b[p] = b < 0 ? 255 : (unsigned char)b;
-    st_t[p] = T(t);
-    st_an[p] = T(an);
-    st_as[p] = T(as);
-  }
+  gather_strided<4>(
+      tid, nthr, npts,
+      [&](int p) {
+        const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+        PointIn r{0.0, {0.0, 0.0, 0.0}};
+        if (y < g.n2) r = point_load(nden, sig, (size_t(x) * g.n2 + y) * n3 + z, N, SIGMA_FROM_GRAD);
+        return r;
+      },
+      [&](int p, const PointIn& r) {
+        int b = -1;
+        double t = 0.0, an = 0.0, as = 0.0;
+        if (y0 + p / n3 < g.n2) q0_state(r.n, point_sigma(r, SIGMA_FROM_GRAD), g.zab, S.q, M, b, t, an, as);
+        st_b[p] = b < 0 ? 255 : (unsigned char)b;
+        st_t[p] = T(t);
+        st_an[p] = T(an);
+        st_as[p] = T(as);
+      });
 
   double acc_n[PPT], acc_s[PPT];
 #pragma unroll
@@ -740,7 +799,7 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
         const int b = st_b[p];
         if (b != 255) {
           const int yl = p / n3, z = p - yl * n3;
-          const T2 F = line[yl * lstride + lidx(z)];
+          const T2 F = line[yl * lstride + lidx<>(z)];
           const T t = st_t[p], an = st_an[p], as = st_as[p];
           const T pa = S.p(fa, b, t), dpa = S.dp(fa, b, t);
           T vn = F.x * (pa + an * dpa);
@@ -797,20 +856,26 @@ k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restri
     load_pair_line(A, g, fa, fb, x, y0, ty, line, lstride, tid, nthr);
     __syncthreads();
     lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
-#pragma unroll 1
-    for (int p = tid; p < npts; p += nthr) {
-      const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
-      if (y < g.n2) {
-        const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-        const T2 v = line[yl * lstride + lidx(z)];
-        if (COMBINE) {
-          out[idx] -= double(v.x) * invN;
-        } else {
-          out[size_t(fa) * N + idx] = double(v.x) * invN;
-          if (fb >= 0) out[size_t(fb) * N + idx] = double(v.y) * invN;
-        }
-      }
-    }
+    // COMBINE reads the previous output; gathered so that those loads are in flight together
+    gather_strided<8>(
+        tid, nthr, npts,
+        [&](int p) {
+          const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+          return (COMBINE && y < g.n2) ? out[(size_t(x) * g.n2 + y) * n3 + z] : 0.0;
+        },
+        [&](int p, double old) {
+          const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+          if (y < g.n2) {
+            const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
+            const T2 v = line[yl * lstride + lidx<>(z)];
+            if (COMBINE) {
+              out[idx] = old - double(v.x) * invN;
+            } else {
+              out[size_t(fa) * N + idx] = double(v.x) * invN;
+              if (fb >= 0) out[size_t(fb) * N + idx] = double(v.y) * invN;
+            }
+          }
+        });
     __syncthreads();
   }
 }

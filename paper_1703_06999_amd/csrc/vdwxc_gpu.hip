@@ -29,6 +29,10 @@ constexpr int kEPT = 8;          // FFT elements per thread in the z and y passe
 #define VDWXC_EPTX 8
 #endif
 constexpr int kEPTX = VDWXC_EPTX;  // FFT elements per thread in the x passes
+#ifndef VDWXC_XPAD
+#define VDWXC_XPAD kNoPad
+#endif
+constexpr int kXPad = VDWXC_XPAD;  // LDS line layout of the contraction pass (no padding)
 constexpr int kMaxThreadsZ = 512;  // z passes
 constexpr int kMaxThreadsY = 1024; // y passes
 constexpr int kMaxThreadsX = 512;  // x passes: one thread per contraction slot
@@ -220,7 +224,7 @@ bool line_launch(int maxt, int n, int other, size_t cplx_bytes, Launch& L) {
   if (long(tile) * n > long(maxt) * kEPT || n > kMaxAxis) return false;
   L.tile = tile;
   L.nthr = threads_for(long(tile) * n, kEPT, maxt);
-  L.lstride = lds_span(n) | 1;   // odd: the transposed tile accesses hit distinct banks
+  L.lstride = lds_span<>(n) | 1;   // odd: the transposed tile accesses hit distinct banks
   L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) + size_t(tile) * L.lstride * cplx_bytes;
   return L.lds + 4096 <= kMaxLds;
 }
@@ -232,7 +236,7 @@ bool xline_launch(int nlines, int n, int slots, size_t cplx_bytes, Launch& L) {
   L.tile = nlines;
   L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(slots, 64)));
   if (n > L.nthr * kEPTX || n > kMaxAxis) return false;
-  L.lstride = lds_span(n);
+  L.lstride = lds_span<>(n);
   L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) +
           std::max<size_t>(size_t(nlines) * L.lstride * cplx_bytes, 16 * sizeof(double));
   return L.lds <= kMaxLds;
@@ -428,12 +432,12 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   if constexpr (sizeof(T) == 4) {
     if (h->ortho) {
       paired = true;
-      hipLaunchKernelGGL((k_xcontract<T, kEPTX, 2>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
+      hipLaunchKernelGGL((k_xcontract<T, kEPTX, 2, kXPad>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
                          Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
     }
   }
   if (!paired)
-    hipLaunchKernelGGL((k_xcontract<T, kEPTX, 1>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
+    hipLaunchKernelGGL((k_xcontract<T, kEPTX, 1, kXPad>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
                        Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
   stage_end(h, VDWXC_STAGE_X_CONTRACT);
   enqueue_ypass<T>(h, h->M, +1, VDWXC_STAGE_Y_INV);
@@ -615,7 +619,13 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     // contraction pass: one thread per slot (k-point, or kx/-kx pair in FP32 orthogonal cells)
     const int slots = (precision == VDWXC_FP32_MIXED && h->ortho) ? h->n1 / 2 + 1 : h->n1;
     Launch& L = precision == VDWXC_FP64 ? h->xl64 : h->xl32;
-    ok = ok && slots <= kMaxThreadsX && xline_launch(nq, h->n1, slots, precision == VDWXC_FP64 ? 16 : 8, L);
+    // the contraction pass keeps its lines unpadded and reads twiddles from global memory, so
+    // its LDS is exactly the N_alpha lines of one column
+    L.tile = nq;
+    L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(slots, 64)));
+    L.lstride = lds_span<kXPad>(h->n1);
+    L.lds = std::max<size_t>(size_t(nq) * L.lstride * (precision == VDWXC_FP64 ? 16 : 8), 16 * sizeof(double));
+    ok = ok && slots <= kMaxThreadsX && h->n1 <= L.nthr * kEPTX && h->n1 <= kMaxAxis && L.lds <= kMaxLds;
   }
   // the z passes keep three per-point values in LDS next to the lines: shrink the tile until
   // they fit (the plain-field z passes use the same tile)
@@ -711,9 +721,9 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
   set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32.lds);
-  set_lds_limit(k_xcontract<double, kEPTX, 1>, h->xl64.lds);
-  set_lds_limit(k_xcontract<float, kEPTX, 1>, h->xl32.lds);
-  set_lds_limit(k_xcontract<float, kEPTX, 2>, h->xl32.lds);
+  set_lds_limit(k_xcontract<double, kEPTX, 1, kXPad>, h->xl64.lds);
+  set_lds_limit(k_xcontract<float, kEPTX, 1, kXPad>, h->xl32.lds);
+  set_lds_limit(k_xcontract<float, kEPTX, 2, kXPad>, h->xl32.lds);
   set_lds_limit(k_xspectral<double, kEPTX, 1, 3>, h->xs64.lds);
   set_lds_limit(k_xspectral<double, kEPTX, 3, 1>, h->xs64.lds);
   set_lds_limit(k_xspectral<float, kEPTX, 3, 1>, h->xs32.lds);

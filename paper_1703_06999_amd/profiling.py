@@ -1,0 +1,111 @@
+"""Summaries of rocprofv3 CSV output for the library's kernels.
+
+    python -m paper_1703_06999_amd.profiling stats  <kernel_stats.csv>  <title>  <command>
+    python -m paper_1703_06999_amd.profiling traffic <fetch counter_collection.csv> \\
+        <write counter_collection.csv> <title> <command>
+
+`stats` tabulates calls and durations per kernel.  `traffic` turns per-dispatch FETCH_SIZE and
+WRITE_SIZE (KiB) into bytes per launch for every stage of an evaluation.  Each counter is scaled
+by what it reads for a plain streaming kernel of known size in the same run: torch's `neg` over a
+buffer of the size given by bench.py's --copy-calibration-mb, which reads and writes that many
+bytes.  The output records the SHA-256 of the kernel sources, so a stale summary can be detected.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import os
+import re
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_1703_06999_amd/csrc/kernels.h", "paper_1703_06999_amd/csrc/fft_lds.h",
+                  "paper_1703_06999_amd/csrc/vdwxc_gpu.hip"]
+
+# kernel symbol -> stage name, in launch order within one potential evaluation
+_STAGE_ORDER = [
+    ("k_theta_zfwd", "theta_zfwd"), ("k_ypass_fwd", "y_fwd"), ("k_xcontract", "x_contract"),
+    ("k_ypass_inv", "y_inv"), ("k_zinv_assemble", "z_assemble"), ("k_energy_reduce", "energy"),
+    ("k_real_zfwd", "div_z"), ("k_ypass_fwd", "div_y"), ("k_xspectral", "div_x"),
+    ("k_ypass_inv", "div_yi"), ("k_real_zinv", "div_zi"),
+]
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _short(name: str) -> str:
+    s = re.sub(r"\(.*", "", name).replace("void ", "").replace("vdwxc::", "")
+    if s.startswith("k_ypass"):
+        s = s.replace("k_ypass", "k_ypass_fwd" if ", -1>" in s else "k_ypass_inv")
+    return s
+
+
+def kernel_stats(path: str, title: str, command: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = [f"# {title}", "", "Command (repository root, one MI355X):", "", "    " + command, "",
+           "Library kernels only; durations in microseconds.", "",
+           "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for r in rows:
+        if "vdwxc::" not in r["Name"]:
+            continue
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def _dispatches(path):
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Dispatch_Id"]))
+    return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows]
+
+
+def _per_stage(disp):
+    """Assign library dispatches to stages in launch order; average over evaluations."""
+    acc = collections.defaultdict(list)
+    lib = [(n, v) for n, v in disp if "vdwxc::" in n and "k_clear_flag" not in n]
+    i = 0
+    while i < len(lib):
+        for sym, stage in _STAGE_ORDER:
+            if i < len(lib) and _short(lib[i][0]).startswith(sym):
+                acc[stage].append(lib[i][1])
+                i += 1
+        if i < len(lib) and not any(_short(lib[i][0]).startswith(s) for s, _ in _STAGE_ORDER[:1]):
+            i += 1   # unexpected kernel: skip it
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic(fetch_csv: str, write_csv: str, title: str, command: str, calib_bytes: float) -> str:
+    fd, wd = _dispatches(fetch_csv), _dispatches(write_csv)
+    cal_f = [v for n, v in fd if "neg_kernel" in n]
+    cal_w = [v for n, v in wd if "neg_kernel" in n]
+    f_scale = calib_bytes / (cal_f[-1] * 1024.0)
+    w_scale = calib_bytes / (cal_w[-1] * 1024.0)
+    fs, ws = _per_stage(fd), _per_stage(wd)
+    out = [f"# {title}", "", "Commands (repository root, one MI355X), one counter per run:", ""]
+    out += ["    " + c for c in command.split(" ;; ")]
+    out += ["", f"source_sha256: {source_hash()}", "",
+            f"Calibration: a plain streaming kernel (torch neg) reads and writes {calib_bytes / 2**20:.0f} MiB;",
+            f"FETCH_SIZE reported {cal_f[-1]:.0f} KiB (scale {f_scale:.4f}), "
+            f"WRITE_SIZE {cal_w[-1]:.0f} KiB (scale {w_scale:.4f}).", "",
+            "| stage | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch |", "|---|---|---|---|"]
+    for _, stage in _STAGE_ORDER:
+        if stage in fs and stage in ws:
+            b = fs[stage] * 1024.0 * f_scale + ws[stage] * 1024.0 * w_scale
+            out.append(f"| `{stage}` | {fs[stage]:.1f} | {ws[stage]:.1f} | {b:.0f} |")
+    return "\n".join(out) + "\n"
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "stats":
+        print(kernel_stats(sys.argv[2], sys.argv[3], sys.argv[4]), end="")
+    elif mode == "traffic":
+        print(traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], float(sys.argv[6]) * 2**20), end="")
+    else:
+        raise SystemExit(__doc__)
