@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fft_lds.h"
 
 namespace vdwxc {
@@ -113,6 +115,29 @@ __device__ __forceinline__ void split_pair(T2 zk, T2 zn, T2& xa, T2& xb) {
   xa = T2{half * (zk.x + zn.x), half * (zk.y - zn.y)};
   xb = T2{half * (zk.y + zn.y), half * (zn.x - zk.x)};
 }
+
+// Minimum waves per SIMD requested from the register allocator, per kernel (1: no constraint).
+#ifndef VDWXC_WPE_THETA
+#define VDWXC_WPE_THETA 1
+#endif
+#ifndef VDWXC_WPE_REALZ
+#define VDWXC_WPE_REALZ 1
+#endif
+#ifndef VDWXC_WPE_Y
+#define VDWXC_WPE_Y 1
+#endif
+#ifndef VDWXC_WPE_XC
+#define VDWXC_WPE_XC 1
+#endif
+#ifndef VDWXC_WPE_XS
+#define VDWXC_WPE_XS 1
+#endif
+#ifndef VDWXC_WPE_ASM
+#define VDWXC_WPE_ASM 1
+#endif
+#ifndef VDWXC_WPE_REALZI
+#define VDWXC_WPE_REALZI 1
+#endif
 
 // ---- strided gathers with several loads in flight -------------------------------------------
 // Thread tid handles the elements e = tid, tid + nthr, ... of [0, tot).  Each group of U of them
@@ -255,7 +280,7 @@ __device__ __forceinline__ double point_sigma(const PointIn& r, bool from_grad) 
 // evaluated once per point in FP64; theta_a = n p_a(q0) is formed in the path's precision T.
 
 template <typename T, int EPT, bool SIGMA_FROM_GRAD>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_THETA)))
 k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
              typename Cx<T>::type* __restrict__ A, int* __restrict__ flag,
              const double* __restrict__ qmesh, const double* __restrict__ mm,
@@ -348,7 +373,7 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
 // input), S = dE/dsigma (src) and g the gradient (aux, [3][N]).
 
 template <typename T, int EPT, int MODE>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_REALZ)))
 k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int nf,
             typename Cx<T>::type* __restrict__ A, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan zp, int ty, int lstride) {
@@ -412,7 +437,7 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
 // Block: TX consecutive x of one (f, kz) (blockIdx.x = x tile, .y = kz, .z = f).
 
 template <typename T, int EPT, int DIR>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_Y)))
 k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __restrict__ dst,
         const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan yp, int tx, int lstride) {
   using T2 = typename Cx<T>::type;
@@ -478,26 +503,64 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 }
 
 // ---- pass 3: x FFT, k-space contraction, inverse x FFT (in place in B) -----------------------
-// Block: the M field lines of one (ky, kz) column (blockIdx.x = ky, .y = kz).
+// Block: the M field lines of one (ky, kz) column (blockIdx.x = kz, .y = ky).  With kz fastest,
+// the blocks resident at one time read and write one contiguous window of each field (the lines
+// of consecutive kz are adjacent in B) instead of lines a whole kz-plane apart.
 // Per k: phi_ab = (1-w) T_j,ab + w T_j+1,ab with |G| = (j + w) dk (Sec. 3 step 3a);
 // F_a = sum_b phi_ab theta_b (step 3b); energy sum_a Re theta_a* F_a (step 3c), weight 2 for kz
-// strictly inside the half spectrum, 1 on its edges.  The table is stored per unordered pair
-// (a <= b) as (T_j, T_j+1) with j contiguous, so one 2-element load gives both nodes of the lerp
-// and lanes with nearby |G| share cache lines.  F is formed one row a at a time, so the M loads
-// of a row are independent and in flight together.
+// strictly inside the half spectrum, 1 on its edges.  phi is symmetric, so each unordered pair
+// (a <= b) is interpolated once and feeds F_a and F_b.  The table holds, per two consecutive
+// pairs and node j (j contiguous), both lerp nodes (T_j, T_j+1) of both pairs: one 16-byte load
+// (FP32) per two pairs, and lanes with nearby |G| share cache lines.  The per-lane table loads go
+// through the texture-address path one lane quad at a time, which made them the limit of this
+// pass when each of the M^2 entries was loaded separately.
 // NPT = 2: in an orthogonal cell |G(kx)| = |G(-kx)|, so a thread handles kx and -kx with one
 // interpolated kernel.
 
-// pair index of (a <= b) for a table dimensioned by kMaxQ
+// pair index of (a <= b) for a table dimensioned by kMaxQ, and its inverse
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * kMaxQ - a * (a - 1) / 2 + (b - a); }
 constexpr int kNumPairs = kMaxQ * (kMaxQ + 1) / 2;
+static_assert(kNumPairs % 2 == 0, "pairs are stored two per table entry");
+struct PairList {
+  int row[kNumPairs], col[kNumPairs];
+  constexpr PairList() : row(), col() {
+    int p = 0;
+    for (int a = 0; a < kMaxQ; ++a)
+      for (int b = a; b < kMaxQ; ++b) {
+        row[p] = a;
+        col[p] = b;
+        ++p;
+      }
+  }
+};
+constexpr PairList kPairs{};
+
+#ifndef VDWXC_XCHUNK
+#define VDWXC_XCHUNK 5
+#endif
+constexpr int kXChunk = VDWXC_XCHUNK;   // table entries per load chunk of the contraction
+
+// kernel table entry: both lerp nodes (T_j, T_j+1) of two consecutive pairs
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+  T x, y, z, w;
+};
+
+// body(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time
+template <int N, typename Body>
+__device__ __forceinline__ void static_for(Body&& body) {
+  if constexpr (N > 0) {
+    static_for<N - 1>(body);
+    body(std::integral_constant<int, N - 1>{});
+  }
+}
 
 // PS: LDS layout of the lines (kNoPad or kSwizzle: no padding).  Without padding and with the twiddles read
 // from global memory, the 20 FP32 lines of a 512-point axis take exactly 80 KB, so two blocks
 // share a CU and one block's HBM loads overlap the other's transforms and contraction.
 template <typename T, int EPT, int NPT, int PS>
-__global__ void __launch_bounds__(512)
-k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ table2,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_XC)))
+k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ table4,
             double* __restrict__ partials, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
   using T2 = typename Cx<T>::type;
@@ -505,7 +568,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   const T2* twl = tw;                       // twiddles from global memory (L1/L2 resident)
   T2* line = reinterpret_cast<T2*>(smem);   // all M field lines of the column
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int ky = blockIdx.x, kz = blockIdx.y, M = g.M, n1 = g.n1;
+  const int kz = blockIdx.x, ky = blockIdx.y, M = g.M, n1 = g.n1;
   const int ls = lds_span<PS>(n1);
   gather_strided<16>(
       tid, nthr, M * n1, [&](int e) { return B[b_index(g, e / n1, ky, kz, e % n1)]; },
@@ -514,65 +577,117 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   const int G = (nthr * EPT) / n1;   // lines per batched transform
   for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1, PS>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
 
-  // this thread's k-points: slot s = tid; NPT = 2 pairs kx with -kx (orthogonal cells)
+  // slots: k-points kx (NPT = 1), or kx/-kx pairs (NPT = 2, orthogonal cells), strided over
+  // the block's threads
   const int nslots = NPT == 2 ? n1 / 2 + 1 : n1;
-  const bool has = tid < nslots;
-  int kx[NPT];
-  bool valid[NPT];
-  kx[0] = tid;
-  valid[0] = has;
-  if (NPT == 2) {
-    kx[NPT - 1] = (n1 - tid) % n1;
-    valid[NPT - 1] = has && tid != 0 && 2 * tid != n1;
-  }
-  T2 th[NPT][kMaxQ];
+  double e = 0.0;
+#pragma unroll 1
+  for (int slot = tid; slot < nslots; slot += nthr) {
+    int kx[NPT];
+    bool valid[NPT];
+    kx[0] = slot;
+    valid[0] = true;
+    if (NPT == 2) {
+      kx[NPT - 1] = (n1 - slot) % n1;
+      valid[NPT - 1] = slot != 0 && 2 * slot != n1;
+    }
+    T2 th[NPT][kMaxQ], F[NPT][kMaxQ];
 #pragma unroll
-  for (int q = 0; q < NPT; ++q)
+    for (int q = 0; q < NPT; ++q)
 #pragma unroll
-    for (int a = 0; a < kMaxQ; ++a) th[q][a] = (a < M && valid[q]) ? line[a * ls + lidx<PS>(kx[q])] : T2{T(0), T(0)};
-
-  double kn;
-  if (NPT == 2) {
-    const double fx = double(tid), fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
-    kn = sqrt(fx * fx * g.bn2[0] + fy * fy * g.bn2[1] + fz * fz * g.bn2[2]);
-  } else {
-    kn = sqrt(gnorm2(g, has ? tid : 0, ky, kz));
-  }
-  const bool inside = kn < g.kmax;
-  const double sc = kn * g.inv_dk;
-  int j = inside ? int(floor(sc)) : 0;
-  if (j > g.nk - 2) j = g.nk - 2;
-  const T w = T(inside ? sc - j : 0.0);
-  const T w0 = inside ? T(1) - w : T(0);
-  const T w1 = inside ? w : T(0);
-  const T2* tp = table2 + j;
-  T e[NPT];
+      for (int a = 0; a < kMaxQ; ++a) {
+        th[q][a] = (a < M && valid[q]) ? line[a * ls + lidx<PS>(kx[q])] : T2{T(0), T(0)};
+        F[q][a] = T2{T(0), T(0)};
+      }
+    double kn;
+    if (NPT == 2) {
+      const double fx = double(slot), fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
+      kn = sqrt(fx * fx * g.bn2[0] + fy * fy * g.bn2[1] + fz * fz * g.bn2[2]);
+    } else {
+      kn = sqrt(gnorm2(g, slot, ky, kz));
+    }
+    const bool inside = kn < g.kmax;
+    const double sc = kn * g.inv_dk;
+    int j = inside ? int(floor(sc)) : 0;
+    if (j > g.nk - 2) j = g.nk - 2;
+    const T w = T(inside ? sc - j : 0.0);
+    const T w0 = inside ? T(1) - w : T(0);
+    const T w1 = inside ? w : T(0);
+    // entry (group, j) = wave-uniform group base + per-lane byte offset of node j, so each load
+    // takes a scalar base and one shared vector offset instead of its own 64-bit address
+    // The groups are loaded in order through one running (wave-uniform) byte offset, laundered
+    // after every step: otherwise all 105 group addresses are computed up front and stay live.
+    const size_t joff = size_t(j) * sizeof(Quad<T>);
+    const size_t gstride = size_t(g.nk) * sizeof(Quad<T>);
+    size_t tcur = 0;
+#define VDWXC_TLOAD(dst)                                                                       \
+  do {                                                                                         \
+    asm volatile("" : "+s"(tcur));                                                             \
+    (dst) = *reinterpret_cast<const Quad<T>*>(reinterpret_cast<const char*>(table4) + tcur + joff); \
+    tcur += gstride;                                                                           \
+  } while (0)
+    // every unordered pair once (phi is symmetric): F_a += phi_ab theta_b, F_b += phi_ab theta_a;
+    // one 16-byte (FP32) load brings both lerp nodes of two pairs
+    // groups of table entries are loaded kXChunk at a time, the next chunk's loads issued before
+    // the current chunk's arithmetic (the scheduling barriers keep the compiler from hoisting
+    // all of them, which would not fit in registers)
+    constexpr int kGroups = kNumPairs / 2;
+    constexpr int kChunks = (kGroups + kXChunk - 1) / kXChunk;
+    Quad<T> buf[2][kXChunk];
 #pragma unroll
-  for (int q = 0; q < NPT; ++q) e[q] = T(0);
-  // one row a at a time: its M table entries are independent loads that can all be in flight
+    for (int i = 0; i < kXChunk; ++i)
+      if (i < kGroups) VDWXC_TLOAD(buf[0][i]);
 #pragma unroll
-  for (int a = 0; a < kMaxQ; ++a) {
-    if (a < M && has) {
-      T2 row[kMaxQ];
+    for (int c = 0; c < kChunks; ++c) {
+      if (c + 1 < kChunks) {
 #pragma unroll
-      for (int b = 0; b < kMaxQ; ++b)
-        row[b] = b < M ? tp[size_t(a <= b ? pair_index(a, b) : pair_index(b, a)) * g.nk] : T2{T(0), T(0)};
-      T2 F[NPT];
-#pragma unroll
-      for (int q = 0; q < NPT; ++q) F[q] = T2{T(0), T(0)};
-#pragma unroll
-      for (int b = 0; b < kMaxQ; ++b) {
-        const T phi = w0 * row[b].x + w1 * row[b].y;
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-          F[q].x += phi * th[q][b].x;
-          F[q].y += phi * th[q][b].y;
-        }
+        for (int i = 0; i < kXChunk; ++i)
+          if ((c + 1) * kXChunk + i < kGroups) VDWXC_TLOAD(buf[(c + 1) & 1][i]);
       }
 #pragma unroll
-      for (int q = 0; q < NPT; ++q) {
-        e[q] += th[q][a].x * F[q].x + th[q][a].y * F[q].y;
-        if (valid[q]) line[a * ls + lidx<PS>(kx[q])] = F[q];
+      for (int i = 0; i < kXChunk; ++i) {
+        const int grp = c * kXChunk + i;
+        if (grp < kGroups) {
+          const Quad<T>& v = buf[c & 1][i];
+          const int a0 = kPairs.row[2 * grp], b0 = kPairs.col[2 * grp];
+          const int a1 = kPairs.row[2 * grp + 1], b1 = kPairs.col[2 * grp + 1];
+          const T phi0 = w0 * v.x + w1 * v.y;
+          const T phi1 = w0 * v.z + w1 * v.w;
+#pragma unroll
+          for (int q = 0; q < NPT; ++q) {
+            F[q][a0].x += phi0 * th[q][b0].x;
+            F[q][a0].y += phi0 * th[q][b0].y;
+            if (a0 != b0) {
+              F[q][b0].x += phi0 * th[q][a0].x;
+              F[q][b0].y += phi0 * th[q][a0].y;
+            }
+            F[q][a1].x += phi1 * th[q][b1].x;
+            F[q][a1].y += phi1 * th[q][b1].y;
+            if (a1 != b1) {
+              F[q][b1].x += phi1 * th[q][a1].x;
+              F[q][b1].y += phi1 * th[q][a1].y;
+            }
+          }
+        }
+      }
+      // pin the accumulators here, so this chunk's arithmetic is not moved below the next
+      // chunk's loads (which would keep every loaded entry live at once)
+#pragma unroll
+      for (int q = 0; q < NPT; ++q)
+#pragma unroll
+        for (int a = 0; a < kMaxQ; ++a) asm volatile("" : "+v"(F[q][a].x), "+v"(F[q][a].y));
+    }
+#undef VDWXC_TLOAD
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      if (valid[q]) {
+#pragma unroll
+        for (int a = 0; a < kMaxQ; ++a) {
+          if (a < M) {
+            e += double(th[q][a].x) * double(F[q][a].x) + double(th[q][a].y) * double(F[q][a].y);
+            line[a * ls + lidx<PS>(kx[q])] = F[q][a];
+          }
+        }
       }
     }
   }
@@ -585,9 +700,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
 
   // block sum of the energy, fixed order: wave shuffles, then the waves in order
   const double wz = (kz == 0 || is_nyquist(kz, g.n3)) ? 1.0 : 2.0;
-  double esum = 0.0;
-#pragma unroll
-  for (int q = 0; q < NPT; ++q) esum += wz * double(e[q]);
+  double esum = wz * e;
   for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
   __syncthreads();
   double* red = reinterpret_cast<double*>(smem);
@@ -604,7 +717,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
 // D_c f = IFFT(i G_c FFT f) with every frequency touching a Nyquist index set to zero.
 
 template <typename T, int EPT, int NIN, int NOUT>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_XS)))
 k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
   using T2 = typename Cx<T>::type;
@@ -613,7 +726,7 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   const T2* twl = stage_twiddles(smem_raw, tw, g.n1, threadIdx.x, blockDim.x);
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int ky = blockIdx.x, kz = blockIdx.y, n1 = g.n1;
+  const int kz = blockIdx.x, ky = blockIdx.y, n1 = g.n1;
   const int ls = lds_span<>(n1);
   gather_strided<8>(
       tid, nthr, NIN * n1, [&](int e) { return B[b_index(g, e / n1, ky, kz, e % n1)]; },
@@ -732,7 +845,7 @@ struct PairPrefetch {
 // registers.
 
 template <typename T, int PPT, int EPT, bool SIGMA_FROM_GRAD>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_ASM)))
 k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __restrict__ nden,
                 const double* __restrict__ sig, double* __restrict__ dedn, double* __restrict__ dedsig,
                 const double* __restrict__ qmesh, const double* __restrict__ mm,
@@ -834,7 +947,7 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
 // ---- pass 5 for plain real fields: out[f] = IFFT/N (COMBINE: out[0] -= IFFT/N) -------------
 
 template <typename T, int EPT, bool COMBINE>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_REALZI)))
 k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restrict__ out,
             const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;

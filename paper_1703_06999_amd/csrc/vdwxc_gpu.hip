@@ -30,9 +30,14 @@ constexpr int kEPT = 8;          // FFT elements per thread in the z and y passe
 #endif
 constexpr int kEPTX = VDWXC_EPTX;  // FFT elements per thread in the x passes
 #ifndef VDWXC_XPAD
-#define VDWXC_XPAD kNoPad
+#define VDWXC_XPAD kSwizzle
 #endif
 constexpr int kXPad = VDWXC_XPAD;  // LDS line layout of the contraction pass (no padding)
+#ifndef VDWXC_XPAIR
+#define VDWXC_XPAIR 0
+#endif
+// FP32, orthogonal cell: one contraction thread serves kx and -kx (same |G|, one interpolation)
+constexpr bool kXPair = VDWXC_XPAIR != 0;
 constexpr int kMaxThreadsZ = 512;  // z passes
 constexpr int kMaxThreadsY = 1024; // y passes
 constexpr int kMaxThreadsX = 512;  // x passes: one thread per contraction slot
@@ -67,8 +72,8 @@ struct vdwxc_ctx {
   // device memory
   double* d_q = nullptr;
   double* d_mm = nullptr;
-  double2* d_table64 = nullptr;   // [pair][j] = (T_j, T_j+1)
-  float2* d_table32 = nullptr;
+  Quad<double>* d_table64 = nullptr;   // [pair / 2][j] = (T_j, T_j+1) of pairs 2g and 2g+1
+  Quad<float>* d_table32 = nullptr;
   double2* d_tw64[3] = {nullptr, nullptr, nullptr};
   float2* d_tw32[3] = {nullptr, nullptr, nullptr};
   void* d_A = nullptr;
@@ -305,7 +310,7 @@ template <> struct Prec<double> {
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs64; }
   static const double2* tw(const vdwxc_ctx* h, int a) { return h->d_tw64[a]; }
-  static const double2* table(const vdwxc_ctx* h) { return h->d_table64; }
+  static const Quad<double>* table(const vdwxc_ctx* h) { return h->d_table64; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta64; }
   static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm64; }
 };
@@ -315,7 +320,7 @@ template <> struct Prec<float> {
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs32; }
   static const float2* tw(const vdwxc_ctx* h, int a) { return h->d_tw32[a]; }
-  static const float2* table(const vdwxc_ctx* h) { return h->d_table32; }
+  static const Quad<float>* table(const vdwxc_ctx* h) { return h->d_table32; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta32; }
   static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm32; }
 };
@@ -386,7 +391,7 @@ void enqueue_spectral(vdwxc_ctx* h, int mode, const double* src, const double* a
                        Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
   stage_end(h, s0);
   enqueue_ypass<T>(h, nin, -1, s0 + 1);
-  dim3 xgrid(h->n2, h->h3);
+  dim3 xgrid(h->h3, h->n2);
   stage_begin(h);
   if (nin == 1)
     hipLaunchKernelGGL((k_xspectral<T, kEPTX, 1, 3>), xgrid, dim3(Lx.nthr), Lx.lds, h->stream, B,
@@ -430,14 +435,14 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   stage_begin(h);
   bool paired = false;
   if constexpr (sizeof(T) == 4) {
-    if (h->ortho) {
+    if (h->ortho && kXPair) {
       paired = true;
-      hipLaunchKernelGGL((k_xcontract<T, kEPTX, 2, kXPad>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
+      hipLaunchKernelGGL((k_xcontract<T, kEPTX, 2, kXPad>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
                          Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
     }
   }
   if (!paired)
-    hipLaunchKernelGGL((k_xcontract<T, kEPTX, 1, kXPad>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
+    hipLaunchKernelGGL((k_xcontract<T, kEPTX, 1, kXPad>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
                        Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
   stage_end(h, VDWXC_STAGE_X_CONTRACT);
   enqueue_ypass<T>(h, h->M, +1, VDWXC_STAGE_Y_INV);
@@ -617,7 +622,7 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
             xline_launch(3, h->n1, h->n1, 16, h->xs64) && xline_launch(3, h->n1, h->n1, 8, h->xs32);
   {
     // contraction pass: one thread per slot (k-point, or kx/-kx pair in FP32 orthogonal cells)
-    const int slots = (precision == VDWXC_FP32_MIXED && h->ortho) ? h->n1 / 2 + 1 : h->n1;
+    const int slots = (precision == VDWXC_FP32_MIXED && h->ortho && kXPair) ? h->n1 / 2 + 1 : h->n1;
     Launch& L = precision == VDWXC_FP64 ? h->xl64 : h->xl32;
     // the contraction pass keeps its lines unpadded and reads twiddles from global memory, so
     // its LDS is exactly the N_alpha lines of one column
@@ -663,21 +668,32 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   if ((e = upload(&h->d_q, h->qmesh.data(), nq)) != hipSuccess) return bail(e, "q-mesh upload");
   if ((e = upload(&h->d_mm, mm.data(), mm.size())) != hipSuccess) return bail(e, "spline upload");
   {
-    // per unordered pair (a <= b): (T_j, T_j+1) for j = 0..nk-1 (the last node repeated)
-    const size_t tn = size_t(kNumPairs) * nk;
-    std::vector<double2> t64(tn, double2{0.0, 0.0});
+    // per unordered pair p = (a <= b): (T_j, T_j+1) for j = 0..nk-1 (the last node repeated);
+    // pairs 2g and 2g+1 share entry [g][j].  Pairs with a or b >= nq stay zero.
+    const size_t tn = size_t(kNumPairs / 2) * nk;
+    std::vector<Quad<double>> t64(tn, Quad<double>{0.0, 0.0, 0.0, 0.0});
     for (int a = 0; a < nq; ++a)
-      for (int b = a; b < nq; ++b)
+      for (int b = a; b < nq; ++b) {
+        const int pr = pair_index(a, b);
         for (int j = 0; j < nk; ++j) {
           const int j1 = std::min(j + 1, nk - 1);
-          t64[size_t(pair_index(a, b)) * nk + j] = double2{table[(size_t(j) * nq + a) * nq + b],
-                                                           table[(size_t(j1) * nq + a) * nq + b]};
+          Quad<double>& q = t64[size_t(pr / 2) * nk + j];
+          const double tj = table[(size_t(j) * nq + a) * nq + b], tj1 = table[(size_t(j1) * nq + a) * nq + b];
+          if (pr % 2 == 0) {
+            q.x = tj;
+            q.y = tj1;
+          } else {
+            q.z = tj;
+            q.w = tj1;
+          }
         }
+      }
     if (precision == VDWXC_FP64) {
       if ((e = upload(&h->d_table64, t64.data(), tn)) != hipSuccess) return bail(e, "table upload");
     } else {
-      std::vector<float2> t32(tn);
-      for (size_t i = 0; i < tn; ++i) t32[i] = float2{float(t64[i].x), float(t64[i].y)};
+      std::vector<Quad<float>> t32(tn);
+      for (size_t i = 0; i < tn; ++i)
+        t32[i] = Quad<float>{float(t64[i].x), float(t64[i].y), float(t64[i].z), float(t64[i].w)};
       if ((e = upload(&h->d_table32, t32.data(), tn)) != hipSuccess) return bail(e, "table upload");
     }
   }
