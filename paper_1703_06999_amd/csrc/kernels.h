@@ -232,6 +232,7 @@ template <typename T>
 __device__ __forceinline__ SplineLds<T> load_spline_lds(unsigned char* smem, size_t off, const double* qmesh,
                                                         const double* mm, int M, int tid, int nthr) {
   SplineLds<T> S;
+  off = (off + 15) & ~size_t(15);   // 16-byte aligned: mmT rows are read two entries at a time
   S.q = reinterpret_cast<double*>(smem + off);
   S.mmT = reinterpret_cast<T*>(smem + off + kMaxQ * sizeof(double));
   S.h = S.mmT + kMaxQ * kMaxQ;
@@ -252,7 +253,7 @@ __device__ __forceinline__ SplineLds<T> load_spline_lds(unsigned char* smem, siz
 // bytes of the spline tables in LDS
 template <typename T>
 constexpr size_t spline_lds_bytes() {
-  return kMaxQ * sizeof(double) + (kMaxQ * kMaxQ + 2 * kMaxQ) * sizeof(T);
+  return 16 + kMaxQ * sizeof(double) + (kMaxQ * kMaxQ + 2 * kMaxQ) * sizeof(T);   // + alignment
 }
 
 // raw inputs of one point: n and either sigma (s[0]) or the three gradient components
@@ -510,10 +511,11 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 // F_a = sum_b phi_ab theta_b (step 3b); energy sum_a Re theta_a* F_a (step 3c), weight 2 for kz
 // strictly inside the half spectrum, 1 on its edges.  phi is symmetric, so each unordered pair
 // (a <= b) is interpolated once and feeds F_a and F_b.  The table holds, per two consecutive
-// pairs and node j (j contiguous), both lerp nodes (T_j, T_j+1) of both pairs: one 16-byte load
-// (FP32) per two pairs, and lanes with nearby |G| share cache lines.  The per-lane table loads go
-// through the texture-address path one lane quad at a time, which made them the limit of this
-// pass when each of the M^2 entries was loaded separately.
+// pairs g and node j (j contiguous), (T_j(2g), T_j(2g+1)); one 16-byte read (FP32) at j brings
+// both lerp nodes of both pairs.  Every lane reads its own nodes, so the table traffic from the
+// caches far exceeds the pass's HBM traffic; it is kept down by reading each pair once, by
+// storing each node once (lanes with nearby |G| share cache lines) and by putting kx and -kx,
+// which have the same |G| in orthogonal cells, in adjacent lanes.
 // NPT = 2: in an orthogonal cell |G(kx)| = |G(-kx)|, so a thread handles kx and -kx with one
 // interpolated kernel.
 
@@ -560,7 +562,7 @@ __device__ __forceinline__ void static_for(Body&& body) {
 // share a CU and one block's HBM loads overlap the other's transforms and contraction.
 template <typename T, int EPT, int NPT, int PS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_XC)))
-k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ table4,
+k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ table2,
             double* __restrict__ partials, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
   using T2 = typename Cx<T>::type;
@@ -585,11 +587,24 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
   for (int slot = tid; slot < nslots; slot += nthr) {
     int kx[NPT];
     bool valid[NPT];
-    kx[0] = slot;
-    valid[0] = true;
     if (NPT == 2) {
+      kx[0] = slot;
+      valid[0] = true;
       kx[NPT - 1] = (n1 - slot) % n1;
       valid[NPT - 1] = slot != 0 && 2 * slot != n1;
+    } else {
+      // kx and -kx in adjacent lanes (same |G| in orthogonal cells, so the same table nodes):
+      // even n1: slots 0, 1 -> 0, n1/2; slot 2m, 2m+1 -> m, n1-m.  odd n1: 0 -> 0; 2m-1, 2m -> m, n1-m.
+      int x;
+      if ((n1 & 1) == 0) {
+        const int m = slot >> 1;
+        x = slot == 0 ? 0 : slot == 1 ? n1 / 2 : ((slot & 1) ? n1 - m : m);
+      } else {
+        const int m = (slot + 1) >> 1;
+        x = slot == 0 ? 0 : ((slot & 1) ? m : n1 - m);
+      }
+      kx[0] = x;
+      valid[0] = true;
     }
     T2 th[NPT][kMaxQ], F[NPT][kMaxQ];
 #pragma unroll
@@ -604,7 +619,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
       const double fx = double(slot), fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
       kn = sqrt(fx * fx * g.bn2[0] + fy * fy * g.bn2[1] + fz * fz * g.bn2[2]);
     } else {
-      kn = sqrt(gnorm2(g, slot, ky, kz));
+      kn = sqrt(gnorm2(g, kx[0], ky, kz));
     }
     const bool inside = kn < g.kmax;
     const double sc = kn * g.inv_dk;
@@ -617,14 +632,16 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     // takes a scalar base and one shared vector offset instead of its own 64-bit address
     // The groups are loaded in order through one running (wave-uniform) byte offset, laundered
     // after every step: otherwise all 105 group addresses are computed up front and stay live.
-    const size_t joff = size_t(j) * sizeof(Quad<T>);
-    const size_t gstride = size_t(g.nk) * sizeof(Quad<T>);
+    // entries j and j+1 of a group are adjacent: one 2-entry read gives both lerp nodes of both
+    // pairs, (T_j(2g), T_j(2g+1), T_j+1(2g), T_j+1(2g+1))
+    const size_t joff = size_t(j) * sizeof(T2);
+    const size_t gstride = size_t(g.nk) * sizeof(T2);
     size_t tcur = 0;
-#define VDWXC_TLOAD(dst)                                                                       \
-  do {                                                                                         \
-    asm volatile("" : "+s"(tcur));                                                             \
-    (dst) = *reinterpret_cast<const Quad<T>*>(reinterpret_cast<const char*>(table4) + tcur + joff); \
-    tcur += gstride;                                                                           \
+#define VDWXC_TLOAD(dst)                                                                        \
+  do {                                                                                          \
+    asm volatile("" : "+s"(tcur));                                                              \
+    __builtin_memcpy(&(dst), reinterpret_cast<const char*>(table2) + tcur + joff, sizeof(Quad<T>)); \
+    tcur += gstride;                                                                            \
   } while (0)
     // every unordered pair once (phi is symmetric): F_a += phi_ab theta_b, F_b += phi_ab theta_a;
     // one 16-byte (FP32) load brings both lerp nodes of two pairs
@@ -651,8 +668,8 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
           const Quad<T>& v = buf[c & 1][i];
           const int a0 = kPairs.row[2 * grp], b0 = kPairs.col[2 * grp];
           const int a1 = kPairs.row[2 * grp + 1], b1 = kPairs.col[2 * grp + 1];
-          const T phi0 = w0 * v.x + w1 * v.y;
-          const T phi1 = w0 * v.z + w1 * v.w;
+          const T phi0 = w0 * v.x + w1 * v.z;
+          const T phi1 = w0 * v.y + w1 * v.w;
 #pragma unroll
           for (int q = 0; q < NPT; ++q) {
             F[q][a0].x += phi0 * th[q][b0].x;
@@ -892,9 +909,22 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
         st_as[p] = T(as);
       });
 
-  double acc_n[PPT], acc_s[PPT];
+  __syncthreads();
+  // Per point, with F_a the inverse transforms and m_c,a = p_a''(q_c):
+  //   sum_a F_a p_a  = u F_b + t F_b+1 + c6 [(u^3-u) X0 + (t^3-t) X1]
+  //   sum_a F_a p_a' = (F_b+1 - F_b)/h + (h/6) [-(3u^2-1) X0 + (3t^2-1) X1]
+  // with X0 = sum_a F_a m_b,a, X1 = sum_a F_a m_b+1,a (u = 1-t).  So each field costs one
+  // F read and the two m entries of its pair, and the spline weights are formed once per point.
+  double X0[PPT], X1[PPT];
+  T Fb[PPT], Fb1[PPT];
+  int bb[PPT];
 #pragma unroll
-  for (int c = 0; c < PPT; ++c) acc_n[c] = acc_s[c] = 0.0;
+  for (int c = 0; c < PPT; ++c) {
+    const int p = tid + c * nthr;
+    bb[c] = p < npts ? st_b[p] : 255;
+    X0[c] = X1[c] = 0.0;
+    Fb[c] = Fb1[c] = T(0);
+  }
   const int npairs = (M + 1) >> 1;
   PairPrefetch<T2, EPT / 2 + 1> pf;
   pf.issue(A, g, 0, M > 1 ? 1 : -1, x, y0, ty, tid, nthr);
@@ -907,24 +937,21 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
     lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
 #pragma unroll
     for (int c = 0; c < PPT; ++c) {
-      const int p = tid + c * nthr;
-      if (p < npts) {
-        const int b = st_b[p];
-        if (b != 255) {
-          const int yl = p / n3, z = p - yl * n3;
-          const T2 F = line[yl * lstride + lidx<>(z)];
-          const T t = st_t[p], an = st_an[p], as = st_as[p];
-          const T pa = S.p(fa, b, t), dpa = S.dp(fa, b, t);
-          T vn = F.x * (pa + an * dpa);
-          T vs = F.x * (as * dpa);
-          if (fb >= 0) {
-            const T pbv = S.p(fb, b, t), dpb = S.dp(fb, b, t);
-            vn += F.y * (pbv + an * dpb);
-            vs += F.y * (as * dpb);
-          }
-          acc_n[c] += double(vn);
-          acc_s[c] += double(vs);
-        }
+      const int b = bb[c];
+      if (b != 255) {
+        const int p = tid + c * nthr;
+        const int yl = p / n3, z = p - yl * n3;
+        const T2 F = line[yl * lstride + lidx<>(z)];
+        // m entries of fields fa, fa+1 at knots b and b+1 (adjacent in the transposed table)
+        const T2 m0 = *reinterpret_cast<const T2*>(S.mmT + b * kMaxQ + fa);
+        const T2 m1 = *reinterpret_cast<const T2*>(S.mmT + (b + 1) * kMaxQ + fa);
+        const T m0y = fb >= 0 ? m0.y : T(0), m1y = fb >= 0 ? m1.y : T(0);
+        X0[c] += double(F.x * m0.x + F.y * m0y);
+        X1[c] += double(F.x * m1.x + F.y * m1y);
+        if (fa == b) Fb[c] = F.x;
+        if (fb == b) Fb[c] = F.y;
+        if (fa == b + 1) Fb1[c] = F.x;
+        if (fb == b + 1) Fb1[c] = F.y;
       }
     }
     __syncthreads();
@@ -936,9 +963,20 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
     if (p < npts) {
       const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
       if (y < g.n2) {
+        double vn = 0.0, vs = 0.0;
+        const int b = bb[c];
+        if (b != 255) {
+          const double t = st_t[p], an = st_an[p], as = st_as[p];
+          const double hh = S.h[b], c6 = S.c6[b], u = 1.0 - t;
+          const double fb0 = Fb[c], fb1 = Fb1[c];
+          const double P = u * fb0 + t * fb1 + c6 * ((u * u * u - u) * X0[c] + (t * t * t - t) * X1[c]);
+          const double D = (fb1 - fb0) / hh + hh * (1.0 / 6.0) * (-(3.0 * u * u - 1.0) * X0[c] + (3.0 * t * t - 1.0) * X1[c]);
+          vn = P + an * D;
+          vs = as * D;
+        }
         const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-        dedn[idx] = acc_n[c] * invN;
-        dedsig[idx] = acc_s[c] * invN;
+        dedn[idx] = vn * invN;
+        dedsig[idx] = vs * invN;
       }
     }
   }

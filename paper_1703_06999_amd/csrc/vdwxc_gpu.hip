@@ -72,8 +72,8 @@ struct vdwxc_ctx {
   // device memory
   double* d_q = nullptr;
   double* d_mm = nullptr;
-  Quad<double>* d_table64 = nullptr;   // [pair / 2][j] = (T_j, T_j+1) of pairs 2g and 2g+1
-  Quad<float>* d_table32 = nullptr;
+  double2* d_table64 = nullptr;   // [pair / 2][j] = (T_j of pair 2g, T_j of pair 2g+1)
+  float2* d_table32 = nullptr;
   double2* d_tw64[3] = {nullptr, nullptr, nullptr};
   float2* d_tw32[3] = {nullptr, nullptr, nullptr};
   void* d_A = nullptr;
@@ -310,7 +310,7 @@ template <> struct Prec<double> {
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs64; }
   static const double2* tw(const vdwxc_ctx* h, int a) { return h->d_tw64[a]; }
-  static const Quad<double>* table(const vdwxc_ctx* h) { return h->d_table64; }
+  static const double2* table(const vdwxc_ctx* h) { return h->d_table64; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta64; }
   static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm64; }
 };
@@ -320,7 +320,7 @@ template <> struct Prec<float> {
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs32; }
   static const float2* tw(const vdwxc_ctx* h, int a) { return h->d_tw32[a]; }
-  static const Quad<float>* table(const vdwxc_ctx* h) { return h->d_table32; }
+  static const float2* table(const vdwxc_ctx* h) { return h->d_table32; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta32; }
   static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm32; }
 };
@@ -668,32 +668,28 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   if ((e = upload(&h->d_q, h->qmesh.data(), nq)) != hipSuccess) return bail(e, "q-mesh upload");
   if ((e = upload(&h->d_mm, mm.data(), mm.size())) != hipSuccess) return bail(e, "spline upload");
   {
-    // per unordered pair p = (a <= b): (T_j, T_j+1) for j = 0..nk-1 (the last node repeated);
-    // pairs 2g and 2g+1 share entry [g][j].  Pairs with a or b >= nq stay zero.
+    // per unordered pair p = (a <= b), node j: T_j; pairs 2g and 2g+1 share entry [g][j], so
+    // entries j, j+1 of one group are the two lerp nodes of both pairs.  Pairs with a or b >= nq
+    // stay zero.
     const size_t tn = size_t(kNumPairs / 2) * nk;
-    std::vector<Quad<double>> t64(tn, Quad<double>{0.0, 0.0, 0.0, 0.0});
+    std::vector<double2> t64(tn, double2{0.0, 0.0});
     for (int a = 0; a < nq; ++a)
       for (int b = a; b < nq; ++b) {
         const int pr = pair_index(a, b);
         for (int j = 0; j < nk; ++j) {
-          const int j1 = std::min(j + 1, nk - 1);
-          Quad<double>& q = t64[size_t(pr / 2) * nk + j];
-          const double tj = table[(size_t(j) * nq + a) * nq + b], tj1 = table[(size_t(j1) * nq + a) * nq + b];
-          if (pr % 2 == 0) {
+          const double tj = table[(size_t(j) * nq + a) * nq + b];
+          double2& q = t64[size_t(pr / 2) * nk + j];
+          if (pr % 2 == 0)
             q.x = tj;
-            q.y = tj1;
-          } else {
-            q.z = tj;
-            q.w = tj1;
-          }
+          else
+            q.y = tj;
         }
       }
     if (precision == VDWXC_FP64) {
       if ((e = upload(&h->d_table64, t64.data(), tn)) != hipSuccess) return bail(e, "table upload");
     } else {
-      std::vector<Quad<float>> t32(tn);
-      for (size_t i = 0; i < tn; ++i)
-        t32[i] = Quad<float>{float(t64[i].x), float(t64[i].y), float(t64[i].z), float(t64[i].w)};
+      std::vector<float2> t32(tn);
+      for (size_t i = 0; i < tn; ++i) t32[i] = float2{float(t64[i].x), float(t64[i].y)};
       if ((e = upload(&h->d_table32, t32.data(), tn)) != hipSuccess) return bail(e, "table upload");
     }
   }
