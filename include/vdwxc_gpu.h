@@ -14,10 +14,9 @@
  *  - Grids: N1 x N2 x N3 points of a periodic cell, stored row-major [N1][N2][N3] (N3 fastest),
  *    point (i,j,k) at r = (i/N1) a1 + (j/N2) a2 + (k/N3) a3.  Each N_i must be >= 1 and a product
  *    of the primes 2, 3, 5, 7.  Limits: N2, N3 <= 2048; the N_alpha lines of one x column must
- *    fit the 160 KiB of LDS of a compute unit, N_alpha * N1 * 16 bytes in FP64 and * 8 bytes in
- *    FP32_MIXED (N1 <= 512 and 1024 at N_alpha = 20), and N1 <= 512 unless the precision is
- *    FP32_MIXED and the cell is orthogonal (then N1 / 2 + 1 <= 512).  vdwxc_init rejects larger
- *    grids with VDWXC_EINVAL.
+ *    fit the 160 KiB of LDS of a compute unit, N_alpha * N1' * 16 bytes in FP64 and * 8 bytes in
+ *    FP32_MIXED with N1' = N1 rounded up to a multiple of 32 (N1 <= 512 and 1024 at
+ *    N_alpha = 20).  vdwxc_init rejects larger grids with VDWXC_EINVAL.
  *  - cell[9]: the lattice vectors a1, a2, a3 as rows, bohr; det(cell) must be > 0.
  *  - Arrays: every array argument of a calculate call is a DEVICE pointer to float64 data owned
  *    by the caller (e.g. a torch tensor); the library never frees or retains it after the call

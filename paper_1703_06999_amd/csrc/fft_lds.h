@@ -45,12 +45,19 @@ __host__ __device__ constexpr int lds_span(int n) {
   }
 }
 
-// Radix schedule of one transform length: radices 8, 4, 2, 3, 5, 7.
+// Radix schedule of one transform length: radices 8, 4, 2, 3, 5, 7.  mnb[s] and mp[s] divide
+// by n / radix[s] and by p_s (the product of the radices before stage s) without a division:
+// x / d = umulhi(x, ceil(2^32 / d)), exact whenever x d < 2^32 (here x < 2^14, d <= 2^11);
+// 0 encodes d = 1.
 struct AxisPlan {
   int n;
   int nst;
   int radix[kMaxStages];
+  unsigned mnb[kMaxStages], mp[kMaxStages];
 };
+
+inline unsigned div_magic(unsigned d) { return d <= 1 ? 0u : unsigned((0x100000000ull + d - 1) / d); }
+__device__ __forceinline__ int fast_div(int x, unsigned m) { return m ? int(__umulhi(unsigned(x), m)) : x; }
 
 template <typename T> struct Cx;
 template <> struct Cx<float> { using type = float2; };
@@ -186,7 +193,7 @@ template <int DIR, typename T2> struct SmallDft<7, DIR, T2> : OddDft<7, DIR, T2>
 // ---- one Stockham stage on LDS lines ---------------------------------------------------------
 
 template <int R, int MAXB, int DIR, int PS, typename T2>
-__device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstride, int p,
+__device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstride, int p, unsigned mnb, unsigned mp,
                                           const T2* __restrict__ tw, int tid, int nthr) {
   const int nb = n / R;
   const int total = nb * nlines;
@@ -198,9 +205,9 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
     const int b = tid + c * nthr;
     dst[c] = -1;
     if (b < total) {
-      const int l = b / nb;
+      const int l = fast_div(b, mnb);
       const int i = b - l * nb;
-      const int k = i % p;
+      const int k = i - fast_div(i, mp) * p;
       const T2* src = buf + l * lstride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[c][r] = src[lidx<PS>(i + r * nb)];
@@ -233,10 +240,10 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
 // lists its radices grouped (all 8s, then 4, 2, 3s, 5s, 7s), so each radix runs in its own loop
 // and the register allocation of one stage kind does not inflate the others.
 template <int R, int EPT, int DIR, int PS, typename T2>
-__device__ __forceinline__ void run_stages(T2* buf, int n, int count, int& p, int nlines, int lstride,
-                                           const T2* __restrict__ tw, int tid, int nthr) {
-  for (int s = 0; s < count; ++s) {
-    fft_stage<R, (EPT + R - 1) / R, DIR, PS>(buf, n, nlines, lstride, p, tw, tid, nthr);
+__device__ __forceinline__ void run_stages(T2* buf, const AxisPlan& plan, int n, int count, int& s0, int& p,
+                                           int nlines, int lstride, const T2* __restrict__ tw, int tid, int nthr) {
+  for (int s = 0; s < count; ++s, ++s0) {
+    fft_stage<R, (EPT + R - 1) / R, DIR, PS>(buf, n, nlines, lstride, p, plan.mnb[s0], plan.mp[s0], tw, tid, nthr);
     p *= R;
   }
 }
@@ -253,13 +260,13 @@ __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
     const int R = plan.radix[s];
     cnt[R == 8 ? 0 : R == 4 ? 1 : R == 2 ? 2 : R == 3 ? 3 : R == 5 ? 4 : 5] += 1;
   }
-  int p = 1;
-  run_stages<8, EPT, DIR, PS>(buf, n, cnt[0], p, nlines, lstride, tw, tid, nthr);
-  run_stages<4, EPT, DIR, PS>(buf, n, cnt[1], p, nlines, lstride, tw, tid, nthr);
-  run_stages<2, EPT, DIR, PS>(buf, n, cnt[2], p, nlines, lstride, tw, tid, nthr);
-  run_stages<3, EPT, DIR, PS>(buf, n, cnt[3], p, nlines, lstride, tw, tid, nthr);
-  run_stages<5, EPT, DIR, PS>(buf, n, cnt[4], p, nlines, lstride, tw, tid, nthr);
-  run_stages<7, EPT, DIR, PS>(buf, n, cnt[5], p, nlines, lstride, tw, tid, nthr);
+  int p = 1, s0 = 0;
+  run_stages<8, EPT, DIR, PS>(buf, plan, n, cnt[0], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<4, EPT, DIR, PS>(buf, plan, n, cnt[1], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<2, EPT, DIR, PS>(buf, plan, n, cnt[2], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<3, EPT, DIR, PS>(buf, plan, n, cnt[3], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<5, EPT, DIR, PS>(buf, plan, n, cnt[4], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<7, EPT, DIR, PS>(buf, plan, n, cnt[5], s0, p, nlines, lstride, tw, tid, nthr);
 }
 
 }  // namespace vdwxc

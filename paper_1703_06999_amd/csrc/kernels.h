@@ -51,15 +51,18 @@ __device__ __forceinline__ void q0_state(double n, double sigma, double zab, con
     ndqdn = ndqds = 0.0;
     return;
   }
+  // k_F r_s = (9 pi / 4)^(1/3), so one cube root and two reciprocals serve all the divisions
   const double kF = cbrt(3.0 * kPi * kPi * n);
-  const double rs = cbrt(3.0 / (4.0 * kPi * n));
+  const double inv_n = 1.0 / n, inv_kF = 1.0 / kF;
+  const double rs = 1.9191582926775130066248 * inv_kF;   // (9 pi / 4)^(1/3) / k_F
   const double sq = sqrt(rs);
   const double Q = 2.0 * kA * (kB1 * sq + kB2 * rs + kB3 * rs * sq + kB4 * rs * rs);
   const double dQ = 2.0 * kA * (0.5 * kB1 / sq + kB2 + 1.5 * kB3 * sq + 2.0 * kB4 * rs);
-  const double lg = log1p(1.0 / Q);
+  const double iQ = 1.0 / Q;
+  const double lg = log1p(iQ);
   const double eps = -2.0 * kA * (1.0 + kAlpha1 * rs) * lg;
-  const double deps = -2.0 * kA * kAlpha1 * lg + 2.0 * kA * (1.0 + kAlpha1 * rs) * dQ / (Q * Q + Q);
-  const double inv_kn2 = 1.0 / (kF * n * n);
+  const double deps = -2.0 * kA * kAlpha1 * lg + 2.0 * kA * (1.0 + kAlpha1 * rs) * dQ * iQ / (Q + 1.0);
+  const double inv_kn2 = inv_kF * inv_n * inv_n;
   const double x = kF - (4.0 * kPi / 3.0) * eps - (zab / 36.0) * sigma * inv_kn2;
   const double tt = x / kSatA;
   double q0, hp;
@@ -82,8 +85,8 @@ __device__ __forceinline__ void q0_state(double n, double sigma, double zab, con
     hp = 0.0;
   }
   if (hp != 0.0) {
-    const double dxdn = kF / (3.0 * n) + (4.0 * kPi / 9.0) * (rs / n) * deps
-                      + (7.0 * zab / 108.0) * sigma * inv_kn2 / n;
+    const double dxdn = (1.0 / 3.0) * kF * inv_n + (4.0 * kPi / 9.0) * rs * inv_n * deps
+                      + (7.0 * zab / 108.0) * sigma * inv_kn2 * inv_n;
     const double dxds = -(zab / 36.0) * inv_kn2;
     ndqdn = n * hp * dxdn;
     ndqds = n * hp * dxds;
@@ -117,17 +120,15 @@ __device__ __forceinline__ void split_pair(T2 zk, T2 zn, T2& xa, T2& xb) {
 }
 
 // Minimum waves per SIMD requested from the register allocator, per kernel (1: no constraint).
+// The theta pass needs <= 128 VGPRs so that two 512-thread blocks share a CU at N3 = 512.
 #ifndef VDWXC_WPE_THETA
-#define VDWXC_WPE_THETA 1
+#define VDWXC_WPE_THETA 4
 #endif
 #ifndef VDWXC_WPE_REALZ
 #define VDWXC_WPE_REALZ 1
 #endif
 #ifndef VDWXC_WPE_Y
 #define VDWXC_WPE_Y 1
-#endif
-#ifndef VDWXC_WPE_XC
-#define VDWXC_WPE_XC 1
 #endif
 #ifndef VDWXC_WPE_XS
 #define VDWXC_WPE_XS 1
@@ -159,6 +160,50 @@ __device__ __forceinline__ void gather_strided(int tid, int nthr, int tot, Get g
     for (int u = 0; u < U; ++u) {
       const int e = e0 + u * nthr;
       if (e < tot) put(e, r[u]);
+    }
+  }
+}
+
+// (q, r) = divmod(e, d) for e = e0, e0 + step, e0 + 2 step, ..., advanced by additions only
+struct DivModStep {
+  int q, r, dq, dr, d;
+  __device__ __forceinline__ DivModStep(int e0, int step, int d_) : d(d_) {
+    q = e0 / d;
+    r = e0 - q * d;
+    dq = step / d;
+    dr = step - dq * d;
+  }
+  __device__ __forceinline__ void next() {
+    q += dq;
+    r += dr;
+    if (r >= d) {
+      r -= d;
+      ++q;
+    }
+  }
+};
+
+// gather_strided over a 2-D index: get(e, q, r) / put(e, q, r, v) receive (q, r) = divmod(e, d)
+template <int U, typename Get, typename Put>
+__device__ __forceinline__ void gather_strided_dm(int tid, int nthr, int tot, int d, Get get, Put put) {
+  using V = decltype(get(0, 0, 0));
+  DivModStep it(tid, nthr, d);
+#pragma unroll 1
+  for (int e0 = tid; e0 < tot; e0 += U * nthr) {
+    V v[U];
+    int qq[U], rr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr;
+      qq[u] = it.q;
+      rr[u] = it.r;
+      if (e < tot) v[u] = get(e, it.q, it.r);
+      it.next();
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < tot) put(e, qq[u], rr[u], v[u]);
     }
   }
 }
@@ -309,16 +354,16 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
   __syncthreads();
 
   bool bad = false;
-  gather_strided<4>(
-      tid, nthr, npts,
-      [&](int p) {
-        const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+  gather_strided_dm<4>(
+      tid, nthr, npts, n3,
+      [&](int, int yl, int z) {
+        const int y = y0 + yl;
         PointIn r{0.0, {0.0, 0.0, 0.0}};
         if (y < g.n2) r = point_load(nden, sig, (size_t(x) * g.n2 + y) * n3 + z, N, SIGMA_FROM_GRAD);
         return r;
       },
-      [&](int p, const PointIn& r) {
-        const int y = y0 + p / n3;
+      [&](int p, int yl, int, const PointIn& r) {
+        const int y = y0 + yl;
         int b = -1;
         double t = 0.0;
         if (y < g.n2) {
@@ -338,9 +383,10 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
 #pragma unroll 1
   for (int pr = 0; pr < npairs; ++pr) {
     const int fa = 2 * pr, fb = 2 * pr + 1;
+    DivModStep it(tid, nthr, n3);
 #pragma unroll 1
-    for (int p = tid; p < npts; p += nthr) {
-      const int yl = p / n3, z = p - yl * n3;
+    for (int p = tid; p < npts; p += nthr, it.next()) {
+      const int yl = it.q, z = it.r;
       const int b = st_b[p];
       T ta = T(0), tb = T(0);
       if (b != 255) {
@@ -353,9 +399,10 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
     const int nout = ty * g.h3;
+    DivModStep ot(tid, nthr, ty);
 #pragma unroll 1
-    for (int e = tid; e < nout; e += nthr) {
-      const int yl = e % ty, kz = e / ty, y = y0 + yl;
+    for (int e = tid; e < nout; e += nthr, ot.next()) {
+      const int yl = ot.r, kz = ot.q, y = y0 + yl;
       if (y < g.n2) {
         const T2 zk = line[yl * lstride + lidx<>(kz)];
         const T2 zn = line[yl * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
@@ -396,10 +443,10 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
     struct Raw {
       double a, b, s;
     };
-    gather_strided<4>(
-        tid, nthr, npts,
-        [&](int p) {
-          const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+    gather_strided_dm<4>(
+        tid, nthr, npts, n3,
+        [&](int, int yl, int z) {
+          const int y = y0 + yl;
           Raw r{0.0, 0.0, 0.0};
           if (y < g.n2) {
             const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
@@ -410,17 +457,17 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
           }
           return r;
         },
-        [&](int p, const Raw& r) {
-          const int yl = p / n3, z = p - yl * n3;
+        [&](int, int yl, int z, const Raw& r) {
           const double s2 = MODE == 0 ? 1.0 : 2.0 * r.s;
           line[yl * lstride + lidx<>(z)] = T2{T(s2 * r.a), T(s2 * r.b)};
         });
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
     const int nout = ty * g.h3;
+    DivModStep ot(tid, nthr, ty);
 #pragma unroll 1
-    for (int e = tid; e < nout; e += nthr) {
-      const int yl = e % ty, kz = e / ty, y = y0 + yl;
+    for (int e = tid; e < nout; e += nthr, ot.next()) {
+      const int yl = ot.r, kz = ot.q, y = y0 + yl;
       if (y < g.n2) {
         const T2 zk = line[yl * lstride + lidx<>(kz)];
         const T2 zn = line[yl * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
@@ -452,34 +499,35 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
   const int x0 = (L % gridDim.x) * tx, kz = (L / gridDim.x) % gridDim.y, f = L / (gridDim.x * gridDim.y);
   const int n2 = g.n2, tot = tx * n2;
   if (DIR < 0) {
-    const size_t base = a_index(g, f, kz, x0, 0);
-    gather_strided<8>(
-        tid, nthr, tot, [&](int e) { return (x0 + e / n2 < g.n1) ? src[base + e] : T2{T(0), T(0)}; },
-        [&](int e, T2 v) {
-          const int xl = e / n2, y = e - xl * n2;
-          line[xl * lstride + lidx<>(y)] = v;
-        });
+    const T2* sbase = src + a_index(g, f, kz, x0, 0);
+    gather_strided_dm<8>(
+        tid, nthr, tot, n2, [&](int e, int xl, int) { return (x0 + xl < g.n1) ? sbase[e] : T2{T(0), T(0)}; },
+        [&](int, int xl, int y, T2 v) { line[xl * lstride + lidx<>(y)] = v; });
   } else {
-    gather_strided<8>(
-        tid, nthr, tot,
-        [&](int e) {
-          const int xl = e % tx, ky = e / tx;
-          return (x0 + xl < g.n1) ? src[b_index(g, f, ky, kz, x0 + xl)] : T2{T(0), T(0)};
-        },
-        [&](int e, T2 v) { line[(e % tx) * lstride + lidx<>(e / tx)] = v; });
+    // B[f][ky][kz][x0 + xl] = sbase[size_t(ky) * ystride + xl]
+    const T2* sbase = src + b_index(g, f, 0, kz, x0);
+    const int ystride = g.h3 * g.n1;
+    gather_strided_dm<8>(
+        tid, nthr, tot, tx,
+        [&](int, int ky, int xl) { return (x0 + xl < g.n1) ? sbase[size_t(ky) * ystride + xl] : T2{T(0), T(0)}; },
+        [&](int, int ky, int xl, T2 v) { line[xl * lstride + lidx<>(ky)] = v; });
   }
   __syncthreads();
   lds_fft<EPT, DIR>(line, yp, tx, lstride, twl, tid, nthr);
   if (DIR < 0) {
-    for (int e = tid; e < tot; e += nthr) {
-      const int xl = e % tx, ky = e / tx;
-      if (x0 + xl < g.n1) dst[b_index(g, f, ky, kz, x0 + xl)] = line[xl * lstride + lidx<>(ky)];
+    T2* dbase = dst + b_index(g, f, 0, kz, x0);
+    const int ystride = g.h3 * g.n1;
+    DivModStep it(tid, nthr, tx);
+    for (int e = tid; e < tot; e += nthr, it.next()) {
+      const int xl = it.r, ky = it.q;
+      if (x0 + xl < g.n1) dbase[size_t(ky) * ystride + xl] = line[xl * lstride + lidx<>(ky)];
     }
   } else {
-    const size_t base = a_index(g, f, kz, x0, 0);
-    for (int e = tid; e < tot; e += nthr) {
-      const int xl = e / n2, y = e - xl * n2;
-      if (x0 + xl < g.n1) dst[base + e] = line[xl * lstride + lidx<>(y)];
+    T2* dbase = dst + a_index(g, f, kz, x0, 0);
+    DivModStep it(tid, nthr, n2);
+    for (int e = tid; e < tot; e += nthr, it.next()) {
+      const int xl = it.q, y = it.r;
+      if (x0 + xl < g.n1) dbase[e] = line[xl * lstride + lidx<>(y)];
     }
   }
 }
@@ -516,8 +564,6 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 // caches far exceeds the pass's HBM traffic; it is kept down by reading each pair once, by
 // storing each node once (lanes with nearby |G| share cache lines) and by putting kx and -kx,
 // which have the same |G| in orthogonal cells, in adjacent lanes.
-// NPT = 2: in an orthogonal cell |G(kx)| = |G(-kx)|, so a thread handles kx and -kx with one
-// interpolated kernel.
 
 // pair index of (a <= b) for a table dimensioned by kMaxQ, and its inverse
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * kMaxQ - a * (a - 1) / 2 + (b - a); }
@@ -548,6 +594,20 @@ struct alignas(4 * sizeof(T)) Quad {
   T x, y, z, w;
 };
 
+// raw buffer resource, dword 3 on gfx9: no format conversion, plain byte addressing
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ void buffer_load_quad(__amdgpu_buffer_rsrc_t r, int voff, int soff, Quad<float>& q) {
+  const auto raw = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  __builtin_memcpy(&q, &raw, sizeof(q));
+}
+__device__ __forceinline__ void buffer_load_quad(__amdgpu_buffer_rsrc_t r, int voff, int soff, Quad<double>& q) {
+  const auto lo = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  const auto hi = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0);
+  __builtin_memcpy(&q.x, &lo, 16);
+  __builtin_memcpy(&q.z, &hi, 16);
+}
+
 // body(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time
 template <int N, typename Body>
 __device__ __forceinline__ void static_for(Body&& body) {
@@ -557,11 +617,12 @@ __device__ __forceinline__ void static_for(Body&& body) {
   }
 }
 
-// PS: LDS layout of the lines (kNoPad or kSwizzle: no padding).  Without padding and with the twiddles read
-// from global memory, the 20 FP32 lines of a 512-point axis take exactly 80 KB, so two blocks
-// share a CU and one block's HBM loads overlap the other's transforms and contraction.
-template <typename T, int EPT, int NPT, int PS>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_XC)))
+// PS: LDS layout of the lines (kNoPad or kSwizzle: no padding).  Without padding and with the
+// twiddles read from global memory, the 20 FP32 lines of a 512-point axis take exactly 80 KB, so
+// two blocks can share a CU; WPE = 4 caps the registers at 128 so that two 512-thread blocks also
+// fit the register file (the launch picks it for such blocks).
+template <typename T, int EPT, int PS, int WPE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ table2,
             double* __restrict__ partials, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
@@ -572,27 +633,25 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int kz = blockIdx.x, ky = blockIdx.y, M = g.M, n1 = g.n1;
   const int ls = lds_span<PS>(n1);
-  gather_strided<16>(
-      tid, nthr, M * n1, [&](int e) { return B[b_index(g, e / n1, ky, kz, e % n1)]; },
-      [&](int e, T2 v) { line[(e / n1) * ls + lidx<PS>(e % n1)] = v; });
+  // field f of this column: cb[f * fstride + x]
+  T2* cb = B + b_index(g, 0, ky, kz, 0);
+  const size_t fstride = size_t(g.n2) * g.h3 * n1;
+  gather_strided_dm<16>(
+      tid, nthr, M * n1, n1, [&](int, int f, int x) { return cb[size_t(f) * fstride + x]; },
+      [&](int, int f, int x, T2 v) { line[f * ls + lidx<PS>(x)] = v; });
   __syncthreads();
   const int G = (nthr * EPT) / n1;   // lines per batched transform
   for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, -1, PS>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
 
-  // slots: k-points kx (NPT = 1), or kx/-kx pairs (NPT = 2, orthogonal cells), strided over
-  // the block's threads
-  const int nslots = NPT == 2 ? n1 / 2 + 1 : n1;
+  // one k-point per slot, slots strided over the block's threads
+  constexpr int NPT = 1;
+  const int nslots = n1;
   double e = 0.0;
 #pragma unroll 1
   for (int slot = tid; slot < nslots; slot += nthr) {
     int kx[NPT];
     bool valid[NPT];
-    if (NPT == 2) {
-      kx[0] = slot;
-      valid[0] = true;
-      kx[NPT - 1] = (n1 - slot) % n1;
-      valid[NPT - 1] = slot != 0 && 2 * slot != n1;
-    } else {
+    {
       // kx and -kx in adjacent lanes (same |G| in orthogonal cells, so the same table nodes):
       // even n1: slots 0, 1 -> 0, n1/2; slot 2m, 2m+1 -> m, n1-m.  odd n1: 0 -> 0; 2m-1, 2m -> m, n1-m.
       int x;
@@ -614,13 +673,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
         th[q][a] = (a < M && valid[q]) ? line[a * ls + lidx<PS>(kx[q])] : T2{T(0), T(0)};
         F[q][a] = T2{T(0), T(0)};
       }
-    double kn;
-    if (NPT == 2) {
-      const double fx = double(slot), fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
-      kn = sqrt(fx * fx * g.bn2[0] + fy * fy * g.bn2[1] + fz * fz * g.bn2[2]);
-    } else {
-      kn = sqrt(gnorm2(g, kx[0], ky, kz));
-    }
+    const double kn = sqrt(gnorm2(g, kx[0], ky, kz));
     const bool inside = kn < g.kmax;
     const double sc = kn * g.inv_dk;
     int j = inside ? int(floor(sc)) : 0;
@@ -634,14 +687,18 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
     // after every step: otherwise all 105 group addresses are computed up front and stay live.
     // entries j and j+1 of a group are adjacent: one 2-entry read gives both lerp nodes of both
     // pairs, (T_j(2g), T_j(2g+1), T_j+1(2g), T_j+1(2g+1))
-    const size_t joff = size_t(j) * sizeof(T2);
-    const size_t gstride = size_t(g.nk) * sizeof(T2);
-    size_t tcur = 0;
-#define VDWXC_TLOAD(dst)                                                                        \
-  do {                                                                                          \
-    asm volatile("" : "+s"(tcur));                                                              \
-    __builtin_memcpy(&(dst), reinterpret_cast<const char*>(table2) + tcur + joff, sizeof(Quad<T>)); \
-    tcur += gstride;                                                                            \
+    // Buffer loads: the lane's byte offset in one VGPR, the group's offset in an SGPR (reads
+    // past the table's end would return zero instead of faulting).
+    const int joff = j * int(sizeof(T2));
+    const int gstride = g.nk * int(sizeof(T2));
+    const __amdgpu_buffer_rsrc_t trs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T2*>(table2), short(0), gstride * (kNumPairs / 2), kBufferWord3);
+    int tcur = 0;
+#define VDWXC_TLOAD(dst)                                                                          \
+  do {                                                                                            \
+    asm volatile("" : "+s"(tcur));                                                                \
+    buffer_load_quad(trs, joff, tcur, (dst));                                                     \
+    tcur += gstride;                                                                              \
   } while (0)
     // every unordered pair once (phi is symmetric): F_a += phi_ab theta_b, F_b += phi_ab theta_a;
     // one 16-byte (FP32) load brings both lerp nodes of two pairs
@@ -710,9 +767,9 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   }
   __syncthreads();
   for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1, PS>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
-  for (int e2 = tid; e2 < M * n1; e2 += nthr) {
-    const int f = e2 / n1, x = e2 - f * n1;
-    B[b_index(g, f, ky, kz, x)] = line[f * ls + lidx<PS>(x)];
+  {
+    DivModStep it(tid, nthr, n1);
+    for (int e2 = tid; e2 < M * n1; e2 += nthr, it.next()) cb[size_t(it.q) * fstride + it.r] = line[it.q * ls + lidx<PS>(it.r)];
   }
 
   // block sum of the energy, fixed order: wave shuffles, then the waves in order
@@ -745,9 +802,11 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int kz = blockIdx.x, ky = blockIdx.y, n1 = g.n1;
   const int ls = lds_span<>(n1);
-  gather_strided<8>(
-      tid, nthr, NIN * n1, [&](int e) { return B[b_index(g, e / n1, ky, kz, e % n1)]; },
-      [&](int e, T2 v) { line[(e / n1) * ls + lidx<>(e % n1)] = v; });
+  T2* cb = B + b_index(g, 0, ky, kz, 0);
+  const size_t fstride = size_t(g.n2) * g.h3 * n1;
+  gather_strided_dm<8>(
+      tid, nthr, NIN * n1, n1, [&](int, int f, int x) { return cb[size_t(f) * fstride + x]; },
+      [&](int, int f, int x, T2 v) { line[f * ls + lidx<>(x)] = v; });
   __syncthreads();
   const int G = (nthr * EPT) / n1;
   for (int l0 = 0; l0 < NIN; l0 += G) lds_fft<EPT, -1>(line + l0 * ls, xp, min(G, NIN - l0), ls, twl, tid, nthr);
@@ -781,9 +840,9 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
   }
   __syncthreads();
   for (int l0 = 0; l0 < NOUT; l0 += G) lds_fft<EPT, +1>(line + l0 * ls, xp, min(G, NOUT - l0), ls, twl, tid, nthr);
-  for (int e = tid; e < NOUT * n1; e += nthr) {
-    const int f = e / n1, x = e - f * n1;
-    B[b_index(g, f, ky, kz, x)] = line[f * ls + lidx<>(x)];
+  {
+    DivModStep it(tid, nthr, n1);
+    for (int e = tid; e < NOUT * n1; e += nthr, it.next()) cb[size_t(it.q) * fstride + it.r] = line[it.q * ls + lidx<>(it.r)];
   }
 }
 
@@ -809,10 +868,10 @@ __device__ __forceinline__ void load_pair_line(const T2* __restrict__ A, const G
   struct Pair {
     T2 a, b;
   };
-  gather_strided<8>(
-      tid, nthr, tot,
-      [&](int e) {
-        const int yl = e % ty, kz = e / ty, y = y0 + yl;
+  gather_strided_dm<8>(
+      tid, nthr, tot, ty,
+      [&](int, int kz, int yl) {
+        const int y = y0 + yl;
         Pair r{T2{T(0), T(0)}, T2{T(0), T(0)}};
         if (y < g.n2) {
           r.a = A[a_index(g, fa, kz, x, y)];
@@ -820,7 +879,7 @@ __device__ __forceinline__ void load_pair_line(const T2* __restrict__ A, const G
         }
         return r;
       },
-      [&](int e, const Pair& r) { store_pair_values(r.a, r.b, e / ty, e % ty, n3, line, lstride); });
+      [&](int, int kz, int yl, const Pair& r) { store_pair_values(r.a, r.b, kz, yl, n3, line, lstride); });
 }
 
 // The half spectra of one field pair for a z-pass tile, held in registers so that the next pair's
@@ -832,12 +891,13 @@ struct PairPrefetch {
                                         int ty, int tid, int nthr) {
     using T = decltype(a[0].x);
     const int tot = ty * g.h3;
+    DivModStep it(tid, nthr, ty);
 #pragma unroll
-    for (int c = 0; c < PF; ++c) {
+    for (int c = 0; c < PF; ++c, it.next()) {
       const int e = tid + c * nthr;
       a[c] = b[c] = T2{T(0), T(0)};
       if (e < tot) {
-        const int yl = e % ty, kz = e / ty, y = y0 + yl;
+        const int yl = it.r, kz = it.q, y = y0 + yl;
         if (y < g.n2) {
           a[c] = A[a_index(g, fa, kz, x, y)];
           if (fb >= 0) b[c] = A[a_index(g, fb, kz, x, y)];
@@ -847,10 +907,11 @@ struct PairPrefetch {
   }
   __device__ __forceinline__ void store(const Geometry& g, int ty, T2* line, int lstride, int tid, int nthr) const {
     const int tot = ty * g.h3;
+    DivModStep it(tid, nthr, ty);
 #pragma unroll
-    for (int c = 0; c < PF; ++c) {
+    for (int c = 0; c < PF; ++c, it.next()) {
       const int e = tid + c * nthr;
-      if (e < tot) store_pair_values(a[c], b[c], e / ty, e % ty, g.n3, line, lstride);
+      if (e < tot) store_pair_values(a[c], b[c], it.q, it.r, g.n3, line, lstride);
     }
   }
 };
@@ -891,18 +952,18 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
   const SplineLds<T> S = load_spline_lds<T>(smem, off, qmesh, mm, M, tid, nthr);
   __syncthreads();
 
-  gather_strided<4>(
-      tid, nthr, npts,
-      [&](int p) {
-        const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+  gather_strided_dm<4>(
+      tid, nthr, npts, n3,
+      [&](int, int yl, int z) {
+        const int y = y0 + yl;
         PointIn r{0.0, {0.0, 0.0, 0.0}};
         if (y < g.n2) r = point_load(nden, sig, (size_t(x) * g.n2 + y) * n3 + z, N, SIGMA_FROM_GRAD);
         return r;
       },
-      [&](int p, const PointIn& r) {
+      [&](int p, int yl, int, const PointIn& r) {
         int b = -1;
         double t = 0.0, an = 0.0, as = 0.0;
-        if (y0 + p / n3 < g.n2) q0_state(r.n, point_sigma(r, SIGMA_FROM_GRAD), g.zab, S.q, M, b, t, an, as);
+        if (y0 + yl < g.n2) q0_state(r.n, point_sigma(r, SIGMA_FROM_GRAD), g.zab, S.q, M, b, t, an, as);
         st_b[p] = b < 0 ? 255 : (unsigned char)b;
         st_t[p] = T(t);
         st_an[p] = T(an);
@@ -917,13 +978,17 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
   // F read and the two m entries of its pair, and the spline weights are formed once per point.
   double X0[PPT], X1[PPT];
   T Fb[PPT], Fb1[PPT];
-  int bb[PPT];
+  int bb[PPT], loff[PPT];   // spline interval (255: none) and LDS line offset of each point
+  {
+    DivModStep it(tid, nthr, n3);
 #pragma unroll
-  for (int c = 0; c < PPT; ++c) {
-    const int p = tid + c * nthr;
-    bb[c] = p < npts ? st_b[p] : 255;
-    X0[c] = X1[c] = 0.0;
-    Fb[c] = Fb1[c] = T(0);
+    for (int c = 0; c < PPT; ++c, it.next()) {
+      const int p = tid + c * nthr;
+      bb[c] = p < npts ? st_b[p] : 255;
+      loff[c] = it.q * lstride + lidx<>(it.r);
+      X0[c] = X1[c] = 0.0;
+      Fb[c] = Fb1[c] = T(0);
+    }
   }
   const int npairs = (M + 1) >> 1;
   PairPrefetch<T2, EPT / 2 + 1> pf;
@@ -939,9 +1004,7 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
     for (int c = 0; c < PPT; ++c) {
       const int b = bb[c];
       if (b != 255) {
-        const int p = tid + c * nthr;
-        const int yl = p / n3, z = p - yl * n3;
-        const T2 F = line[yl * lstride + lidx<>(z)];
+        const T2 F = line[loff[c]];
         // m entries of fields fa, fa+1 at knots b and b+1 (adjacent in the transposed table)
         const T2 m0 = *reinterpret_cast<const T2*>(S.mmT + b * kMaxQ + fa);
         const T2 m1 = *reinterpret_cast<const T2*>(S.mmT + (b + 1) * kMaxQ + fa);
@@ -957,11 +1020,12 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
     __syncthreads();
   }
   const double invN = 1.0 / double(N);
+  DivModStep ot(tid, nthr, n3);
 #pragma unroll
-  for (int c = 0; c < PPT; ++c) {
+  for (int c = 0; c < PPT; ++c, ot.next()) {
     const int p = tid + c * nthr;
     if (p < npts) {
-      const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+      const int yl = ot.q, z = ot.r, y = y0 + yl;
       if (y < g.n2) {
         double vn = 0.0, vs = 0.0;
         const int b = bb[c];
@@ -1008,14 +1072,14 @@ k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restri
     __syncthreads();
     lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
     // COMBINE reads the previous output; gathered so that those loads are in flight together
-    gather_strided<8>(
-        tid, nthr, npts,
-        [&](int p) {
-          const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+    gather_strided_dm<8>(
+        tid, nthr, npts, n3,
+        [&](int, int yl, int z) {
+          const int y = y0 + yl;
           return (COMBINE && y < g.n2) ? out[(size_t(x) * g.n2 + y) * n3 + z] : 0.0;
         },
-        [&](int p, double old) {
-          const int yl = p / n3, z = p - yl * n3, y = y0 + yl;
+        [&](int, int yl, int z, double old) {
+          const int y = y0 + yl;
           if (y < g.n2) {
             const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
             const T2 v = line[yl * lstride + lidx<>(z)];

@@ -33,11 +33,6 @@ constexpr int kEPTX = VDWXC_EPTX;  // FFT elements per thread in the x passes
 #define VDWXC_XPAD kSwizzle
 #endif
 constexpr int kXPad = VDWXC_XPAD;  // LDS line layout of the contraction pass (no padding)
-#ifndef VDWXC_XPAIR
-#define VDWXC_XPAIR 0
-#endif
-// FP32, orthogonal cell: one contraction thread serves kx and -kx (same |G|, one interpolation)
-constexpr bool kXPair = VDWXC_XPAIR != 0;
 constexpr int kMaxThreadsZ = 512;  // z passes
 constexpr int kMaxThreadsY = 1024; // y passes
 constexpr int kMaxThreadsX = 512;  // x passes: one thread per contraction slot
@@ -68,6 +63,7 @@ struct vdwxc_ctx {
   AxisPlan plan[3]{};
   Launch zl64, zl32, yl64, yl32, xl64, xl32, xs64, xs32;
   size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
+  bool x_capped = false;   // launch the register-capped contraction kernel
   bool ortho = false;
   // device memory
   double* d_q = nullptr;
@@ -126,7 +122,14 @@ bool factor_axis(int n, AxisPlan& p) {
       m /= r;
     }
   }
-  return m == 1;
+  if (m != 1) return false;
+  int prod = 1;
+  for (int s = 0; s < p.nst; ++s) {
+    p.mnb[s] = div_magic(unsigned(n / p.radix[s]));
+    p.mp[s] = div_magic(unsigned(prod));
+    prod *= p.radix[s];
+  }
+  return true;
 }
 
 double det3(const double* c) {
@@ -433,16 +436,16 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   stage_end(h, VDWXC_STAGE_THETA_ZFWD);
   enqueue_ypass<T>(h, h->M, -1, VDWXC_STAGE_Y_FWD);
   stage_begin(h);
-  bool paired = false;
+  bool launched = false;
   if constexpr (sizeof(T) == 4) {
-    if (h->ortho && kXPair) {
-      paired = true;
-      hipLaunchKernelGGL((k_xcontract<T, kEPTX, 2, kXPad>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
-                         Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+    if (h->x_capped) {
+      hipLaunchKernelGGL((k_xcontract<T, kEPTX, kXPad, 4>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream,
+                         B, Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+      launched = true;
     }
   }
-  if (!paired)
-    hipLaunchKernelGGL((k_xcontract<T, kEPTX, 1, kXPad>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
+  if (!launched)
+    hipLaunchKernelGGL((k_xcontract<T, kEPTX, kXPad, 1>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
                        Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
   stage_end(h, VDWXC_STAGE_X_CONTRACT);
   enqueue_ypass<T>(h, h->M, +1, VDWXC_STAGE_Y_INV);
@@ -621,16 +624,17 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
             line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64) && line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32) &&
             xline_launch(3, h->n1, h->n1, 16, h->xs64) && xline_launch(3, h->n1, h->n1, 8, h->xs32);
   {
-    // contraction pass: one thread per slot (k-point, or kx/-kx pair in FP32 orthogonal cells)
-    const int slots = (precision == VDWXC_FP32_MIXED && h->ortho && kXPair) ? h->n1 / 2 + 1 : h->n1;
+    // contraction pass: one thread per k-point up to kMaxThreadsX (the kernel strides beyond)
     Launch& L = precision == VDWXC_FP64 ? h->xl64 : h->xl32;
     // the contraction pass keeps its lines unpadded and reads twiddles from global memory, so
     // its LDS is exactly the N_alpha lines of one column
     L.tile = nq;
-    L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(slots, 64)));
+    L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(h->n1, 64)));
     L.lstride = lds_span<kXPad>(h->n1);
     L.lds = std::max<size_t>(size_t(nq) * L.lstride * (precision == VDWXC_FP64 ? 16 : 8), 16 * sizeof(double));
-    ok = ok && slots <= kMaxThreadsX && h->n1 <= L.nthr * kEPTX && h->n1 <= kMaxAxis && L.lds <= kMaxLds;
+    ok = ok && h->n1 <= L.nthr * kEPTX && h->n1 <= kMaxAxis && L.lds <= kMaxLds;
+    // blocks of 7 or more waves: with the register cap two of them share a CU, if LDS allows
+    h->x_capped = precision == VDWXC_FP32_MIXED && L.nthr >= 448 && 2 * L.lds <= kMaxLds;
   }
   // the z passes keep three per-point values in LDS next to the lines: shrink the tile until
   // they fit (the plain-field z passes use the same tile)
@@ -733,9 +737,9 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
   set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32.lds);
-  set_lds_limit(k_xcontract<double, kEPTX, 1, kXPad>, h->xl64.lds);
-  set_lds_limit(k_xcontract<float, kEPTX, 1, kXPad>, h->xl32.lds);
-  set_lds_limit(k_xcontract<float, kEPTX, 2, kXPad>, h->xl32.lds);
+  set_lds_limit(k_xcontract<double, kEPTX, kXPad, 1>, h->xl64.lds);
+  set_lds_limit(k_xcontract<float, kEPTX, kXPad, 1>, h->xl32.lds);
+  set_lds_limit(k_xcontract<float, kEPTX, kXPad, 4>, h->xl32.lds);
   set_lds_limit(k_xspectral<double, kEPTX, 1, 3>, h->xs64.lds);
   set_lds_limit(k_xspectral<double, kEPTX, 3, 1>, h->xs64.lds);
   set_lds_limit(k_xspectral<float, kEPTX, 3, 1>, h->xs32.lds);
