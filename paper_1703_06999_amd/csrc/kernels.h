@@ -134,7 +134,7 @@ __device__ __forceinline__ void split_pair(T2 zk, T2 zn, T2& xa, T2& xb) {
 #define VDWXC_WPE_XS 1
 #endif
 #ifndef VDWXC_WPE_ASM
-#define VDWXC_WPE_ASM 1
+#define VDWXC_WPE_ASM 4   // FP32 assembly: <= 128 VGPRs, two 512-thread blocks per CU
 #endif
 #ifndef VDWXC_WPE_REALZI
 #define VDWXC_WPE_REALZI 1
@@ -255,21 +255,6 @@ struct SplineLds {
   T* h;        // [M-1]
   T* c6;       // [M-1]
   double* q;   // [M]
-  __device__ __forceinline__ T p(int a, int b, T t) const {
-    const T u = T(1) - t;
-    T v = c6[b] * ((u * u * u - u) * mmT[b * kMaxQ + a] + (t * t * t - t) * mmT[(b + 1) * kMaxQ + a]);
-    if (a == b) v += u;
-    if (a == b + 1) v += t;
-    return v;
-  }
-  __device__ __forceinline__ T dp(int a, int b, T t) const {
-    const T u = T(1) - t;
-    const T hh = h[b];
-    T v = hh * T(1.0 / 6.0) * (-(T(3) * u * u - T(1)) * mmT[b * kMaxQ + a] + (T(3) * t * t - T(1)) * mmT[(b + 1) * kMaxQ + a]);
-    if (a == b) v -= T(1) / hh;
-    if (a == b + 1) v += T(1) / hh;
-    return v;
-  }
 };
 
 // carve the shared tables out of LDS (after `off` bytes) and fill them from global memory
@@ -390,15 +375,25 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
       const int b = st_b[p];
       T ta = T(0), tb = T(0);
       if (b != 255) {
-        const T t = st_t[p], nv = st_n[p];
-        ta = nv * S.p(fa, b, t);
-        if (fb < M) tb = nv * S.p(fb, b, t);
+        // theta_a = n p_a = n [u d_ab + t d_a,b+1 + c6 ((u^3-u) m_b,a + (t^3-t) m_b+1,a)]: the
+        // weights once per point, the m entries of fields fa, fa+1 in one read per knot
+        const T t = st_t[p], nv = st_n[p], u = T(1) - t;
+        const T c = S.c6[b] * nv;
+        const T wa = c * (u * u * u - u), wb = c * (t * t * t - t);
+        const T2 m0 = *reinterpret_cast<const T2*>(S.mmT + b * kMaxQ + fa);
+        const T2 m1 = *reinterpret_cast<const T2*>(S.mmT + (b + 1) * kMaxQ + fa);
+        const T nu = nv * u, nt = nv * t;
+        ta = wa * m0.x + wb * m1.x + (fa == b ? nu : T(0)) + (fa == b + 1 ? nt : T(0));
+        tb = fb < M ? wa * m0.y + wb * m1.y + (fb == b ? nu : T(0)) + (fb == b + 1 ? nt : T(0)) : T(0);
       }
       line[yl * lstride + lidx<>(z)] = T2{ta, tb};
     }
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
     const int nout = ty * g.h3;
+    // A[f][kz][x][y0 + yl] = Aa[kz * kzstride + yl] (field fa), Aa[fstride + ...] (field fb)
+    T2* Aa = A + a_index(g, fa, 0, x, y0);
+    const size_t kzstride = size_t(g.n1) * g.n2, fstride = size_t(g.h3) * kzstride;
     DivModStep ot(tid, nthr, ty);
 #pragma unroll 1
     for (int e = tid; e < nout; e += nthr, ot.next()) {
@@ -408,8 +403,9 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
         const T2 zn = line[yl * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
         T2 xa, xb;
         split_pair(zk, zn, xa, xb);
-        A[a_index(g, fa, kz, x, y)] = xa;
-        if (fb < M) A[a_index(g, fb, kz, x, y)] = xb;
+        T2* dst = Aa + size_t(kz) * kzstride + yl;
+        dst[0] = xa;
+        if (fb < M) dst[fstride] = xb;
       }
     }
     __syncthreads();
@@ -923,7 +919,7 @@ struct PairPrefetch {
 // registers.
 
 template <typename T, int PPT, int EPT, bool SIGMA_FROM_GRAD>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_ASM)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? VDWXC_WPE_ASM : 1)))
 k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __restrict__ nden,
                 const double* __restrict__ sig, double* __restrict__ dedn, double* __restrict__ dedsig,
                 const double* __restrict__ qmesh, const double* __restrict__ mm,

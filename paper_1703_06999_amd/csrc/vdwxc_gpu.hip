@@ -23,7 +23,7 @@ using namespace vdwxc;
 
 namespace {
 
-constexpr int kPPT = 8;          // grid points per thread in the z passes
+constexpr int kEPTA = 4;         // grid points (and FFT elements) per thread in the z assembly
 constexpr int kEPT = 8;          // FFT elements per thread in the z and y passes
 #ifndef VDWXC_EPTX
 #define VDWXC_EPTX 8
@@ -61,7 +61,7 @@ struct vdwxc_ctx {
   int device = 0;
   Geometry geo{};
   AxisPlan plan[3]{};
-  Launch zl64, zl32, yl64, yl32, xl64, xl32, xs64, xs32;
+  Launch zl64, zl32, za64, za32, yl64, yl32, xl64, xl32, xs64, xs32;
   size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
   bool x_capped = false;   // launch the register-capped contraction kernel
   bool ortho = false;
@@ -226,12 +226,12 @@ int threads_for(long items, int ept, int maxt) {
 
 // TILE lines of length n in one block (TILE <= min(16, other)), padded stride n + 1; the LDS
 // size includes the twiddle table of the axis
-bool line_launch(int maxt, int n, int other, size_t cplx_bytes, Launch& L) {
+bool line_launch(int maxt, int n, int other, size_t cplx_bytes, Launch& L, int ept = kEPT) {
   int tile = std::min(kLineTile, std::max(1, other));
-  while (tile > 1 && long(tile) * n > long(maxt) * kEPT) tile /= 2;
-  if (long(tile) * n > long(maxt) * kEPT || n > kMaxAxis) return false;
+  while (tile > 1 && long(tile) * n > long(maxt) * ept) tile /= 2;
+  if (long(tile) * n > long(maxt) * ept || n > kMaxAxis) return false;
   L.tile = tile;
-  L.nthr = threads_for(long(tile) * n, kEPT, maxt);
+  L.nthr = threads_for(long(tile) * n, ept, maxt);
   L.lstride = lds_span<>(n) | 1;   // odd: the transposed tile accesses hit distinct banks
   L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) + size_t(tile) * L.lstride * cplx_bytes;
   return L.lds + 4096 <= kMaxLds;
@@ -309,6 +309,7 @@ template <typename T>
 struct Prec;
 template <> struct Prec<double> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl64; }
+  static const Launch& za(const vdwxc_ctx* h) { return h->za64; }
   static const Launch& y(const vdwxc_ctx* h) { return h->yl64; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs64; }
@@ -319,6 +320,7 @@ template <> struct Prec<double> {
 };
 template <> struct Prec<float> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl32; }
+  static const Launch& za(const vdwxc_ctx* h) { return h->za32; }
   static const Launch& y(const vdwxc_ctx* h) { return h->yl32; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs32; }
@@ -450,14 +452,16 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   stage_end(h, VDWXC_STAGE_X_CONTRACT);
   enqueue_ypass<T>(h, h->M, +1, VDWXC_STAGE_Y_INV);
   stage_begin(h);
+  const Launch& La = Prec<T>::za(h);
+  const dim3 agrid((h->n2 + La.tile - 1) / La.tile, h->n1);
   if (sig_from_grad)
-    hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, true>), zgrid, dim3(Lz.nthr), lds_asm, h->stream, A, n,
-                       sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile,
-                       Lz.lstride);
+    hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, true>), agrid, dim3(La.nthr), lds_asm, h->stream, A, n,
+                       sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile,
+                       La.lstride);
   else
-    hipLaunchKernelGGL((k_zinv_assemble<T, kPPT, kEPT, false>), zgrid, dim3(Lz.nthr), lds_asm, h->stream, A, n,
-                       sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile,
-                       Lz.lstride);
+    hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, false>), agrid, dim3(La.nthr), lds_asm, h->stream, A, n,
+                       sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile,
+                       La.lstride);
   stage_end(h, VDWXC_STAGE_Z_ASSEMBLE);
   const double N = double(h->n1) * h->n2 * h->n3;
   stage_begin(h);
@@ -638,23 +642,32 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   }
   // the z passes keep three per-point values in LDS next to the lines: shrink the tile until
   // they fit (the plain-field z passes use the same tile)
-  auto fit_state = [&](Launch& L, size_t cplx, size_t real) {
+  auto fit_state = [&](Launch& L, size_t cplx, size_t real, int ept) {
     while (L.tile > 1) {
       const size_t npts = size_t(L.tile) * h->n3;
       const size_t need = L.lds + npts * 3 * real + ((npts + 15) & ~size_t(15)) + 4096;
       if (need <= kMaxLds) break;
       L.tile /= 2;
-      L.nthr = threads_for(long(L.tile) * h->n3, kEPT, kMaxThreadsZ);
+      L.nthr = threads_for(long(L.tile) * h->n3, ept, kMaxThreadsZ);
       L.lds = ((size_t(h->n3) * cplx + 15) & ~size_t(15)) + size_t(L.tile) * L.lstride * cplx;
     }
   };
-  fit_state(h->zl64, 16, 8);
-  fit_state(h->zl32, 8, 4);
+  // the assembly pass: its own tile, 4 points per thread
+  ok = ok && line_launch(kMaxThreadsZ, h->n3, h->n2, 16, h->za64, kEPTA) &&
+       line_launch(kMaxThreadsZ, h->n3, h->n2, 8, h->za32, kEPTA);
+  fit_state(h->zl64, 16, 8, kEPT);
+  fit_state(h->zl32, 8, 4, kEPT);
+  fit_state(h->za64, 16, 8, kEPTA);
+  fit_state(h->za32, 8, 4, kEPTA);
   h->lds_theta64 = zstate_lds<double>(h->zl64, h->n3, 2);
   h->lds_theta32 = zstate_lds<float>(h->zl32, h->n3, 2);
-  h->lds_asm64 = zstate_lds<double>(h->zl64, h->n3, 3);
-  h->lds_asm32 = zstate_lds<float>(h->zl32, h->n3, 3);
+  h->lds_asm64 = zstate_lds<double>(h->za64, h->n3, 3);
+  h->lds_asm32 = zstate_lds<float>(h->za32, h->n3, 3);
   ok = ok && h->lds_asm64 <= kMaxLds && h->lds_asm32 <= kMaxLds;
+  // assembly: every thread covers its kEPTA points and its share of the half spectrum (pair
+  // prefetch depth kEPTA / 2 + 1)
+  for (const Launch* L : {&h->za64, &h->za32})
+    ok = ok && long(L->nthr) * kEPTA >= long(L->tile) * h->n3 && long(L->nthr) * (kEPTA / 2 + 1) >= long(L->tile) * h->h3;
   if (!ok) {
     release(h);
     return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
@@ -723,10 +736,10 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_theta_zfwd<double, kEPT, true>, h->lds_theta64);
   set_lds_limit(k_theta_zfwd<float, kEPT, false>, h->lds_theta32);
   set_lds_limit(k_theta_zfwd<float, kEPT, true>, h->lds_theta32);
-  set_lds_limit(k_zinv_assemble<double, kPPT, kEPT, false>, h->lds_asm64);
-  set_lds_limit(k_zinv_assemble<double, kPPT, kEPT, true>, h->lds_asm64);
-  set_lds_limit(k_zinv_assemble<float, kPPT, kEPT, false>, h->lds_asm32);
-  set_lds_limit(k_zinv_assemble<float, kPPT, kEPT, true>, h->lds_asm32);
+  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA, false>, h->lds_asm64);
+  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA, true>, h->lds_asm64);
+  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA, false>, h->lds_asm32);
+  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA, true>, h->lds_asm32);
   set_lds_limit(k_real_zfwd<double, kEPT, 0>, h->zl64.lds);
   set_lds_limit(k_real_zfwd<double, kEPT, 1>, h->zl64.lds);
   set_lds_limit(k_real_zfwd<float, kEPT, 1>, h->zl32.lds);
