@@ -555,11 +555,9 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 // F_a = sum_b phi_ab theta_b (step 3b); energy sum_a Re theta_a* F_a (step 3c), weight 2 for kz
 // strictly inside the half spectrum, 1 on its edges.  phi is symmetric, so each unordered pair
 // (a <= b) is interpolated once and feeds F_a and F_b.  The table holds, per two consecutive
-// pairs g and node j (j contiguous), (T_j(2g), T_j(2g+1)); one 16-byte read (FP32) at j brings
-// both lerp nodes of both pairs.  Every lane reads its own nodes, so the table traffic from the
-// caches far exceeds the pass's HBM traffic; it is kept down by reading each pair once, by
-// storing each node once (lanes with nearby |G| share cache lines) and by putting kx and -kx,
-// which have the same |G| in orthogonal cells, in adjacent lanes.
+// pairs g and node j (j contiguous), T_j and T_j+1 - T_j of both pairs: one 16-byte read (FP32)
+// per two pairs and one FMA per interpolation.  Every lane reads its own nodes; kx and -kx, which
+// have the same |G| in orthogonal cells, sit in adjacent lanes and share them.
 
 // pair index of (a <= b) for a table dimensioned by kMaxQ, and its inverse
 __host__ __device__ constexpr int pair_index(int a, int b) { return a * kMaxQ - a * (a - 1) / 2 + (b - a); }
@@ -619,7 +617,7 @@ __device__ __forceinline__ void static_for(Body&& body) {
 // fit the register file (the launch picks it for such blocks).
 template <typename T, int EPT, int PS, int WPE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ table2,
+k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ table4,
             double* __restrict__ partials, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
   using T2 = typename Cx<T>::type;
@@ -670,25 +668,27 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
         F[q][a] = T2{T(0), T(0)};
       }
     const double kn = sqrt(gnorm2(g, kx[0], ky, kz));
+    // phi = 0 for |G| >= k_max: there the thetas are taken as zero, so F = 0 and no energy
     const bool inside = kn < g.kmax;
+    if (!inside) {
+#pragma unroll
+      for (int a = 0; a < kMaxQ; ++a) th[0][a] = T2{T(0), T(0)};
+    }
     const double sc = kn * g.inv_dk;
     int j = inside ? int(floor(sc)) : 0;
     if (j > g.nk - 2) j = g.nk - 2;
     const T w = T(inside ? sc - j : 0.0);
-    const T w0 = inside ? T(1) - w : T(0);
-    const T w1 = inside ? w : T(0);
-    // entry (group, j) = wave-uniform group base + per-lane byte offset of node j, so each load
-    // takes a scalar base and one shared vector offset instead of its own 64-bit address
-    // The groups are loaded in order through one running (wave-uniform) byte offset, laundered
-    // after every step: otherwise all 105 group addresses are computed up front and stay live.
-    // entries j and j+1 of a group are adjacent: one 2-entry read gives both lerp nodes of both
-    // pairs, (T_j(2g), T_j(2g+1), T_j+1(2g), T_j+1(2g+1))
-    // Buffer loads: the lane's byte offset in one VGPR, the group's offset in an SGPR (reads
-    // past the table's end would return zero instead of faulting).
-    const int joff = j * int(sizeof(T2));
-    const int gstride = g.nk * int(sizeof(T2));
+    // Table entry (group g, node j) = T_j of pairs 2g and 2g+1, then their differences
+    // T_j+1 - T_j, so phi = T_j + w (T_j+1 - T_j) is one FMA.  Buffer loads: the lane's node
+    // offset in one VGPR, the group's offset in an SGPR, advanced through one running offset
+    // that is laundered after every step (otherwise all 105 group offsets are formed up front
+    // and stay live).  Each pair is read and interpolated once (phi is symmetric) and feeds
+    // F_a += phi theta_b and F_b += phi theta_a.  The loads run kXChunk at a time, the next
+    // chunk's issued before the current chunk's arithmetic.
+    const int joff = j * int(sizeof(Quad<T>));
+    const int gstride = g.nk * int(sizeof(Quad<T>));
     const __amdgpu_buffer_rsrc_t trs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<T2*>(table2), short(0), gstride * (kNumPairs / 2), kBufferWord3);
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<Quad<T>*>(table4), short(0), gstride * (kNumPairs / 2), kBufferWord3);
     int tcur = 0;
 #define VDWXC_TLOAD(dst)                                                                          \
   do {                                                                                            \
@@ -696,11 +696,6 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
     buffer_load_quad(trs, joff, tcur, (dst));                                                     \
     tcur += gstride;                                                                              \
   } while (0)
-    // every unordered pair once (phi is symmetric): F_a += phi_ab theta_b, F_b += phi_ab theta_a;
-    // one 16-byte (FP32) load brings both lerp nodes of two pairs
-    // groups of table entries are loaded kXChunk at a time, the next chunk's loads issued before
-    // the current chunk's arithmetic (the scheduling barriers keep the compiler from hoisting
-    // all of them, which would not fit in registers)
     constexpr int kGroups = kNumPairs / 2;
     constexpr int kChunks = (kGroups + kXChunk - 1) / kXChunk;
     Quad<T> buf[2][kXChunk];
@@ -721,8 +716,8 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
           const Quad<T>& v = buf[c & 1][i];
           const int a0 = kPairs.row[2 * grp], b0 = kPairs.col[2 * grp];
           const int a1 = kPairs.row[2 * grp + 1], b1 = kPairs.col[2 * grp + 1];
-          const T phi0 = w0 * v.x + w1 * v.z;
-          const T phi1 = w0 * v.y + w1 * v.w;
+          const T phi0 = v.x + w * v.z;
+          const T phi1 = v.y + w * v.w;
 #pragma unroll
           for (int q = 0; q < NPT; ++q) {
             F[q][a0].x += phi0 * th[q][b0].x;

@@ -28,7 +28,12 @@ constexpr int kEPT = 8;          // FFT elements per thread in the z and y passe
 #ifndef VDWXC_EPTX
 #define VDWXC_EPTX 8
 #endif
-constexpr int kEPTX = VDWXC_EPTX;  // FFT elements per thread in the x passes
+constexpr int kEPTX = VDWXC_EPTX;  // FFT elements per thread in the spectral x passes
+#ifndef VDWXC_EPTC
+#define VDWXC_EPTC 20
+#endif
+// FFT elements per thread in the contraction pass: all 20 lines of a column in one transform
+constexpr int kEPTC = VDWXC_EPTC;
 #ifndef VDWXC_XPAD
 #define VDWXC_XPAD kSwizzle
 #endif
@@ -68,8 +73,8 @@ struct vdwxc_ctx {
   // device memory
   double* d_q = nullptr;
   double* d_mm = nullptr;
-  double2* d_table64 = nullptr;   // [pair / 2][j] = (T_j of pair 2g, T_j of pair 2g+1)
-  float2* d_table32 = nullptr;
+  Quad<double>* d_table64 = nullptr;   // [pair / 2][j]: T_j of pairs 2g, 2g+1, then T_j+1 - T_j
+  Quad<float>* d_table32 = nullptr;
   double2* d_tw64[3] = {nullptr, nullptr, nullptr};
   float2* d_tw32[3] = {nullptr, nullptr, nullptr};
   void* d_A = nullptr;
@@ -314,7 +319,7 @@ template <> struct Prec<double> {
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs64; }
   static const double2* tw(const vdwxc_ctx* h, int a) { return h->d_tw64[a]; }
-  static const double2* table(const vdwxc_ctx* h) { return h->d_table64; }
+  static const Quad<double>* table(const vdwxc_ctx* h) { return h->d_table64; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta64; }
   static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm64; }
 };
@@ -325,7 +330,7 @@ template <> struct Prec<float> {
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs32; }
   static const float2* tw(const vdwxc_ctx* h, int a) { return h->d_tw32[a]; }
-  static const float2* table(const vdwxc_ctx* h) { return h->d_table32; }
+  static const Quad<float>* table(const vdwxc_ctx* h) { return h->d_table32; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta32; }
   static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm32; }
 };
@@ -441,13 +446,13 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   bool launched = false;
   if constexpr (sizeof(T) == 4) {
     if (h->x_capped) {
-      hipLaunchKernelGGL((k_xcontract<T, kEPTX, kXPad, 4>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream,
+      hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 4>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream,
                          B, Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
       launched = true;
     }
   }
   if (!launched)
-    hipLaunchKernelGGL((k_xcontract<T, kEPTX, kXPad, 1>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
+    hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 1>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
                        Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
   stage_end(h, VDWXC_STAGE_X_CONTRACT);
   enqueue_ypass<T>(h, h->M, +1, VDWXC_STAGE_Y_INV);
@@ -636,7 +641,7 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(h->n1, 64)));
     L.lstride = lds_span<kXPad>(h->n1);
     L.lds = std::max<size_t>(size_t(nq) * L.lstride * (precision == VDWXC_FP64 ? 16 : 8), 16 * sizeof(double));
-    ok = ok && h->n1 <= L.nthr * kEPTX && h->n1 <= kMaxAxis && L.lds <= kMaxLds;
+    ok = ok && h->n1 <= L.nthr * kEPTC && h->n1 <= kMaxAxis && L.lds <= kMaxLds;
     // blocks of 7 or more waves: with the register cap two of them share a CU, if LDS allows
     h->x_capped = precision == VDWXC_FP32_MIXED && L.nthr >= 448 && 2 * L.lds <= kMaxLds;
   }
@@ -685,28 +690,33 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   if ((e = upload(&h->d_q, h->qmesh.data(), nq)) != hipSuccess) return bail(e, "q-mesh upload");
   if ((e = upload(&h->d_mm, mm.data(), mm.size())) != hipSuccess) return bail(e, "spline upload");
   {
-    // per unordered pair p = (a <= b), node j: T_j; pairs 2g and 2g+1 share entry [g][j], so
-    // entries j, j+1 of one group are the two lerp nodes of both pairs.  Pairs with a or b >= nq
-    // stay zero.
+    // per unordered pair p = (a <= b) and node j: T_j and T_j+1 - T_j (0 at the last node);
+    // pairs 2g and 2g+1 share entry [g][j] = (T_j(2g), T_j(2g+1), D_j(2g), D_j(2g+1)).  Pairs
+    // with a or b >= nq stay zero.
     const size_t tn = size_t(kNumPairs / 2) * nk;
-    std::vector<double2> t64(tn, double2{0.0, 0.0});
+    std::vector<Quad<double>> t64(tn, Quad<double>{0.0, 0.0, 0.0, 0.0});
     for (int a = 0; a < nq; ++a)
       for (int b = a; b < nq; ++b) {
         const int pr = pair_index(a, b);
         for (int j = 0; j < nk; ++j) {
           const double tj = table[(size_t(j) * nq + a) * nq + b];
-          double2& q = t64[size_t(pr / 2) * nk + j];
-          if (pr % 2 == 0)
+          const double dj = j + 1 < nk ? table[(size_t(j + 1) * nq + a) * nq + b] - tj : 0.0;
+          Quad<double>& q = t64[size_t(pr / 2) * nk + j];
+          if (pr % 2 == 0) {
             q.x = tj;
-          else
+            q.z = dj;
+          } else {
             q.y = tj;
+            q.w = dj;
+          }
         }
       }
     if (precision == VDWXC_FP64) {
       if ((e = upload(&h->d_table64, t64.data(), tn)) != hipSuccess) return bail(e, "table upload");
     } else {
-      std::vector<float2> t32(tn);
-      for (size_t i = 0; i < tn; ++i) t32[i] = float2{float(t64[i].x), float(t64[i].y)};
+      std::vector<Quad<float>> t32(tn);
+      for (size_t i = 0; i < tn; ++i)
+        t32[i] = Quad<float>{float(t64[i].x), float(t64[i].y), float(t64[i].z), float(t64[i].w)};
       if ((e = upload(&h->d_table32, t32.data(), tn)) != hipSuccess) return bail(e, "table upload");
     }
   }
@@ -750,9 +760,9 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
   set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32.lds);
-  set_lds_limit(k_xcontract<double, kEPTX, kXPad, 1>, h->xl64.lds);
-  set_lds_limit(k_xcontract<float, kEPTX, kXPad, 1>, h->xl32.lds);
-  set_lds_limit(k_xcontract<float, kEPTX, kXPad, 4>, h->xl32.lds);
+  set_lds_limit(k_xcontract<double, kEPTC, kXPad, 1>, h->xl64.lds);
+  set_lds_limit(k_xcontract<float, kEPTC, kXPad, 1>, h->xl32.lds);
+  set_lds_limit(k_xcontract<float, kEPTC, kXPad, 4>, h->xl32.lds);
   set_lds_limit(k_xspectral<double, kEPTX, 1, 3>, h->xs64.lds);
   set_lds_limit(k_xspectral<double, kEPTX, 3, 1>, h->xs64.lds);
   set_lds_limit(k_xspectral<float, kEPTX, 3, 1>, h->xs32.lds);

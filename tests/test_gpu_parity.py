@@ -116,6 +116,32 @@ def test_partials_ragged_grids(dev, precision, grid, L, seed):
     close_fields(ds.cpu(), ds_ref, tol["fs"], "dedsigma", n, tol["wl1s"])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("m", [7, 12, 2])
+def test_smaller_q_meshes(dev, precision, m):
+    """q-meshes shorter than 20 points, odd and even: the last field unpaired in the z passes,
+    and kernel-table pairs beyond the mesh empty in the contraction."""
+    say(f"[q-mesh M={m}] {precision}")
+    kt = inputs.synthetic_kernel_table(qmesh=inputs.log_qmesh(m))
+    grid, L = (24, 18, 30), 7.0
+    n, g, sigma = ragged_case(grid, L, 40 + m, floor=1e-4)
+    cell = inputs.cubic_cell(L)
+    from paper_1703_06999_amd import vdwxc
+    f = vdwxc.Functional(grid, cell, flavour="DF1", precision=precision, table=kt)
+    E_ref, dn_ref, ds_ref = vdwdf.energy_and_partials(n.numpy(), sigma.numpy(), cell, kt)
+    E, dn, ds = f.calculate(n.to(dev), sigma.to(dev))
+    tol = TOL[precision]
+    say(f"    E rel error {abs(E - E_ref) / abs(E_ref):.3e}")
+    assert abs(E - E_ref) <= tol["e"] * abs(E_ref), (E, E_ref)
+    close_fields(dn.cpu(), dn_ref, tol["f"], "dedn", n, tol["wl1"])
+    close_fields(ds.cpu(), ds_ref, tol["fs"], "dedsigma", n, tol["wl1s"])
+    Ev_ref, v_ref, _, _ = vdwdf.potential(n.numpy(), cell, kt, grad=g.numpy())
+    Ev, v = f.potential(n.to(dev), g.to(dev))
+    f.close()
+    assert abs(Ev - Ev_ref) <= tol["e"] * abs(Ev_ref)
+    close_fields(v.cpu(), v_ref, tol["f"], "v", n, tol["wl1"])
+
+
 def test_hello_world(dev):
     say("[hello world] 1x2x2")
     import json, os
