@@ -578,7 +578,7 @@ struct PairList {
 constexpr PairList kPairs{};
 
 #ifndef VDWXC_XCHUNK
-#define VDWXC_XCHUNK 5
+#define VDWXC_XCHUNK 3
 #endif
 constexpr int kXChunk = VDWXC_XCHUNK;   // table entries per load chunk of the contraction
 

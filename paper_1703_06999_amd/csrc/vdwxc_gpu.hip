@@ -34,6 +34,9 @@ constexpr int kEPTX = VDWXC_EPTX;  // FFT elements per thread in the spectral x 
 #endif
 // FFT elements per thread in the contraction pass: all 20 lines of a column in one transform
 constexpr int kEPTC = VDWXC_EPTC;
+#ifndef VDWXC_XCAP_MIN_THREADS
+#define VDWXC_XCAP_MIN_THREADS 64   // smallest contraction block that uses the register-capped kernel
+#endif
 #ifndef VDWXC_XPAD
 #define VDWXC_XPAD kSwizzle
 #endif
@@ -642,8 +645,9 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     L.lstride = lds_span<kXPad>(h->n1);
     L.lds = std::max<size_t>(size_t(nq) * L.lstride * (precision == VDWXC_FP64 ? 16 : 8), 16 * sizeof(double));
     ok = ok && h->n1 <= L.nthr * kEPTC && h->n1 <= kMaxAxis && L.lds <= kMaxLds;
-    // blocks of 7 or more waves: with the register cap two of them share a CU, if LDS allows
-    h->x_capped = precision == VDWXC_FP32_MIXED && L.nthr >= 448 && 2 * L.lds <= kMaxLds;
+    // FP32: the register-capped kernel (128 VGPRs) fits four waves per SIMD, e.g. two 512-thread
+    // blocks per CU at N1 = 512 when LDS allows; measured faster at every size tried
+    h->x_capped = precision == VDWXC_FP32_MIXED && L.nthr >= VDWXC_XCAP_MIN_THREADS && 2 * L.lds <= kMaxLds;
   }
   // the z passes keep three per-point values in LDS next to the lines: shrink the tile until
   // they fit (the plain-field z passes use the same tile)

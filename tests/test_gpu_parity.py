@@ -117,10 +117,11 @@ def test_partials_ragged_grids(dev, precision, grid, L, seed):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("m", [7, 12, 2])
+@pytest.mark.parametrize("m", [7, 12, 4])
 def test_smaller_q_meshes(dev, precision, m):
-    """q-meshes shorter than 20 points, odd and even: the last field unpaired in the z passes,
-    and kernel-table pairs beyond the mesh empty in the contraction."""
+    """q-meshes shorter than 20 points (4 is the smallest the library takes), odd and even: the
+    last field unpaired in the z passes, and kernel-table pairs beyond the mesh empty in the
+    contraction."""
     say(f"[q-mesh M={m}] {precision}")
     kt = inputs.synthetic_kernel_table(qmesh=inputs.log_qmesh(m))
     grid, L = (24, 18, 30), 7.0
