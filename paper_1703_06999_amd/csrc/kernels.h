@@ -39,6 +39,13 @@ struct Geometry {
   double bn2[3];           // |b_i|^2 (used when the cell is orthogonal)
 };
 
+// four values of the path's precision in one aligned load: a kernel-table entry, or the spline
+// state of a grid point
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+  T x, y, z, w;
+};
+
 // ---- q0, saturation and the helper splines (per grid point, FP64) ----------------------------
 
 // q0 of the appendix with the saturation h_5, clamped below the first mesh point.  Returns the
@@ -118,6 +125,10 @@ __device__ __forceinline__ void split_pair(T2 zk, T2 zn, T2& xa, T2& xb) {
   xa = T2{half * (zk.x + zn.x), half * (zk.y - zn.y)};
   xb = T2{half * (zk.y + zn.y), half * (zn.x - zk.x)};
 }
+
+#ifndef VDWXC_THETA_U
+#define VDWXC_THETA_U 2   // density/gradient loads in flight per thread in the theta pass
+#endif
 
 // Minimum waves per SIMD requested from the register allocator, per kernel (1: no constraint).
 // The theta pass needs <= 128 VGPRs so that two 512-thread blocks share a CU at N3 = 512.
@@ -308,12 +319,13 @@ __device__ __forceinline__ double point_sigma(const PointIn& r, bool from_grad) 
 // ---- pass 1: q0 + splines + forward z FFT (theta fields) ------------------------------------
 // Block: one x plane, TY consecutive y lines.  LDS: the TY pair lines, then per point the spline
 // interval b (uint8, 255 = vacuum), position t and density n, then the spline tables.  q0 is
-// evaluated once per point in FP64; theta_a = n p_a(q0) is formed in the path's precision T.
+// evaluated once per point in FP64; theta_a = n p_a(q0) is formed in the path's precision T.  The
+// point's state (t, n dq0/dn, n dq0/dsigma, b) also goes to `state` for the inverse z pass.
 
 template <typename T, int EPT, bool SIGMA_FROM_GRAD>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_THETA)))
 k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
-             typename Cx<T>::type* __restrict__ A, int* __restrict__ flag,
+             typename Cx<T>::type* __restrict__ A, Quad<T>* __restrict__ state, int* __restrict__ flag,
              const double* __restrict__ qmesh, const double* __restrict__ mm,
              const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
@@ -339,7 +351,7 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
   __syncthreads();
 
   bool bad = false;
-  gather_strided_dm<4>(
+  gather_strided_dm<VDWXC_THETA_U>(
       tid, nthr, npts, n3,
       [&](int, int yl, int z) {
         const int y = y0 + yl;
@@ -347,15 +359,17 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
         if (y < g.n2) r = point_load(nden, sig, (size_t(x) * g.n2 + y) * n3 + z, N, SIGMA_FROM_GRAD);
         return r;
       },
-      [&](int p, int yl, int, const PointIn& r) {
+      [&](int p, int yl, int z, const PointIn& r) {
         const int y = y0 + yl;
         int b = -1;
         double t = 0.0;
         if (y < g.n2) {
           const double sv = point_sigma(r, SIGMA_FROM_GRAD);
           bad |= !(r.n == r.n) || !(sv == sv);
-          double d1, d2;
-          q0_state(r.n, sv, g.zab, S.q, M, b, t, d1, d2);
+          double an, as;
+          q0_state(r.n, sv, g.zab, S.q, M, b, t, an, as);
+          // the point's spline state for the inverse z pass: (t, n dq0/dn, n dq0/dsigma, b)
+          state[(size_t(x) * g.n2 + y) * n3 + z] = Quad<T>{T(t), T(an), T(as), T(b < 0 ? 255 : b)};
         }
         st_b[p] = b < 0 ? 255 : (unsigned char)b;
         st_t[p] = T(t);
@@ -582,11 +596,6 @@ constexpr PairList kPairs{};
 #endif
 constexpr int kXChunk = VDWXC_XCHUNK;   // table entries per load chunk of the contraction
 
-// kernel table entry: both lerp nodes (T_j, T_j+1) of two consecutive pairs
-template <typename T>
-struct alignas(4 * sizeof(T)) Quad {
-  T x, y, z, w;
-};
 
 // raw buffer resource, dword 3 on gfx9: no format conversion, plain byte addressing
 constexpr int kBufferWord3 = 0x00020000;
@@ -909,14 +918,14 @@ struct PairPrefetch {
 
 // ---- pass 5: inverse z FFT + assembly of dE/dn, dE/dsigma (eqs. dedn, dedsigma) -------------
 // dE/dn = sum_a F_a [p_a + n p_a' dq0/dn],  dE/dsigma = sum_a F_a n p_a' dq0/dsigma, with F_a(r)
-// from the inverse transforms (1/N applied here).  q0 is recomputed once per point in FP64; the
-// per-point spline state (b, t, n dq0/dn, n dq0/dsigma) sits in LDS, the two sums in FP64
-// registers.
+// from the inverse transforms (1/N applied here).  The per-point spline state (b, t, n dq0/dn,
+// n dq0/dsigma), computed in FP64 by the forward theta pass and stored in the path's precision,
+// is read once into LDS; the two sums sit in FP64 registers.
 
-template <typename T, int PPT, int EPT, bool SIGMA_FROM_GRAD>
+template <typename T, int PPT, int EPT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? VDWXC_WPE_ASM : 1)))
-k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __restrict__ nden,
-                const double* __restrict__ sig, double* __restrict__ dedn, double* __restrict__ dedsig,
+k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __restrict__ state,
+                double* __restrict__ dedn, double* __restrict__ dedsig,
                 const double* __restrict__ qmesh, const double* __restrict__ mm,
                 const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
@@ -943,22 +952,20 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const double* __rest
   const SplineLds<T> S = load_spline_lds<T>(smem, off, qmesh, mm, M, tid, nthr);
   __syncthreads();
 
+  // the spline state of each point, as the forward theta pass left it
   gather_strided_dm<4>(
       tid, nthr, npts, n3,
       [&](int, int yl, int z) {
         const int y = y0 + yl;
-        PointIn r{0.0, {0.0, 0.0, 0.0}};
-        if (y < g.n2) r = point_load(nden, sig, (size_t(x) * g.n2 + y) * n3 + z, N, SIGMA_FROM_GRAD);
-        return r;
+        Quad<T> q{T(0), T(0), T(0), T(255)};
+        if (y < g.n2) q = state[(size_t(x) * g.n2 + y) * n3 + z];
+        return q;
       },
-      [&](int p, int yl, int, const PointIn& r) {
-        int b = -1;
-        double t = 0.0, an = 0.0, as = 0.0;
-        if (y0 + yl < g.n2) q0_state(r.n, point_sigma(r, SIGMA_FROM_GRAD), g.zab, S.q, M, b, t, an, as);
-        st_b[p] = b < 0 ? 255 : (unsigned char)b;
-        st_t[p] = T(t);
-        st_an[p] = T(an);
-        st_as[p] = T(as);
+      [&](int p, int, int, const Quad<T>& q) {
+        st_b[p] = (unsigned char)int(q.w);
+        st_t[p] = q.x;
+        st_an[p] = q.y;
+        st_as[p] = q.z;
       });
 
   __syncthreads();
@@ -1088,9 +1095,11 @@ k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restri
 
 // ---- energy: fixed-order sum of the per-column partials --------------------------------------
 
+// flag[0] is raised by the theta pass on a NaN input; it is moved to flag[1] (the evaluation's
+// result, read by the host) and cleared here, so the next evaluation starts from zero.
 __global__ void __launch_bounds__(512)
-k_energy_reduce(const double* __restrict__ partials, int nparts, double scale,
-                const int* __restrict__ flag, double* __restrict__ out) {
+k_energy_reduce(const double* __restrict__ partials, int nparts, double scale, int* __restrict__ flag,
+                double* __restrict__ out) {
   __shared__ double red[16];
   const int tid = threadIdx.x;
   double s = 0.0;
@@ -1101,12 +1110,11 @@ k_energy_reduce(const double* __restrict__ partials, int nparts, double scale,
   if (tid == 0) {
     double tot = 0.0;
     for (int w = 0; w < (int(blockDim.x) + 63) / 64; ++w) tot += red[w];
-    out[0] = (*flag != 0) ? __builtin_nan("") : tot * scale;
+    const int bad = flag[0];
+    out[0] = bad != 0 ? __builtin_nan("") : tot * scale;
+    flag[1] = bad;
+    flag[0] = 0;
   }
-}
-
-__global__ void k_clear_flag(int* flag) {
-  if (threadIdx.x == 0) *flag = 0;
 }
 
 }  // namespace vdwxc

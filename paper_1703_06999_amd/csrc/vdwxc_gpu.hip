@@ -84,6 +84,7 @@ struct vdwxc_ctx {
   void* d_B = nullptr;
   size_t buf_bytes = 0;
   double* d_S = nullptr;       // dE/dsigma of the potential entry
+  void* d_state = nullptr;     // per-point spline state, Quad<T> [N], theta pass -> assembly
   double* d_G = nullptr;       // spectral gradient [3][N]
   double* d_partials = nullptr;
   double* d_energy = nullptr;  // energy of the synchronous entries
@@ -264,6 +265,9 @@ size_t zstate_lds(const Launch& L, int n3, int per_point_values) {
   return L.lds + npts * per_point_values * sizeof(T) + ((npts + 15) & ~size_t(15)) + spline_lds_bytes<T>();
 }
 
+// bytes per grid point of the spline state passed from the theta pass to the assembly
+size_t state_bytes(vdwxc_precision p) { return p == VDWXC_FP64 ? sizeof(Quad<double>) : sizeof(Quad<float>); }
+
 size_t complex_buffer_bytes(int n1, int n2, int n3, vdwxc_precision p, int M) {
   const size_t nk = size_t(n1) * n2 * (n3 / 2 + 1);
   const size_t fields = (p == VDWXC_FP64) ? std::max(M, 3) * 16 : std::max<size_t>(M * 8, 3 * 16);
@@ -293,7 +297,7 @@ void release(vdwxc_ctx* h) {
   auto f = [](void* p) { if (p) (void)hipFree(p); };
   f(h->d_q); f(h->d_mm); f(h->d_table64); f(h->d_table32);
   for (int i = 0; i < 3; ++i) { f(h->d_tw64[i]); f(h->d_tw32[i]); }
-  f(h->d_A); f(h->d_B); f(h->d_S); f(h->d_G); f(h->d_partials); f(h->d_energy); f(h->d_flag);
+  f(h->d_A); f(h->d_B); f(h->d_S); f(h->d_state); f(h->d_G); f(h->d_partials); f(h->d_energy); f(h->d_flag);
   if (h->h_energy) (void)hipHostFree(h->h_energy);
   if (h->h_flag) (void)hipHostFree(h->h_flag);
   delete h;
@@ -437,11 +441,12 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
   stage_begin(h);
   const size_t lds_theta = Prec<T>::theta_lds(h), lds_asm = Prec<T>::asm_lds(h);
+  Quad<T>* state = static_cast<Quad<T>*>(h->d_state);
   if (sig_from_grad)
-    hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, true>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A,
+    hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, true>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A, state,
                        h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
   else
-    hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, false>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A,
+    hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, false>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A, state,
                        h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
   stage_end(h, VDWXC_STAGE_THETA_ZFWD);
   enqueue_ypass<T>(h, h->M, -1, VDWXC_STAGE_Y_FWD);
@@ -462,14 +467,8 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   stage_begin(h);
   const Launch& La = Prec<T>::za(h);
   const dim3 agrid((h->n2 + La.tile - 1) / La.tile, h->n1);
-  if (sig_from_grad)
-    hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, true>), agrid, dim3(La.nthr), lds_asm, h->stream, A, n,
-                       sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile,
-                       La.lstride);
-  else
-    hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, false>), agrid, dim3(La.nthr), lds_asm, h->stream, A, n,
-                       sig, dedn, dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile,
-                       La.lstride);
+  hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state, dedn,
+                     dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile, La.lstride);
   stage_end(h, VDWXC_STAGE_Z_ASSEMBLE);
   const double N = double(h->n1) * h->n2 * h->n3;
   stage_begin(h);
@@ -492,7 +491,6 @@ vdwxc_status finish_launch(vdwxc_ctx* h) {
 vdwxc_status run_partials(vdwxc_ctx* h, const double* n, const double* sigma, double* dedn, double* dedsig,
                           double* energy_dev) {
   HIP_TRY(h, hipSetDevice(h->device));
-  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, h->stream, h->d_flag);
   if (h->precision == VDWXC_FP64)
     enqueue_main<double>(h, n, sigma, false, dedn, dedsig, energy_dev);
   else
@@ -502,7 +500,6 @@ vdwxc_status run_partials(vdwxc_ctx* h, const double* n, const double* sigma, do
 
 vdwxc_status run_potential(vdwxc_ctx* h, const double* n, const double* grad, double* v, double* energy_dev) {
   HIP_TRY(h, hipSetDevice(h->device));
-  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, h->stream, h->d_flag);
   const double* g = grad;
   if (!g) {
     // the gradient feeds q0, so it is taken in FP64 in both precisions
@@ -521,7 +518,7 @@ vdwxc_status run_potential(vdwxc_ctx* h, const double* n, const double* grad, do
 
 vdwxc_status read_energy(vdwxc_ctx* h, double* energy_host) {
   HIP_TRY(h, hipMemcpyAsync(h->h_energy, h->d_energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->h_flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->h_flag, h->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   if (*h->h_flag) return fail(h, VDWXC_EINVAL, "density or gradient input contains NaN");
   *energy_host = *h->h_energy;
@@ -555,7 +552,8 @@ size_t vdwxc_workspace_bytes(const int grid[3], vdwxc_precision precision, int n
   if (!grid || grid[0] < 1 || grid[1] < 1 || grid[2] < 1 || nq < 1) return 0;
   const size_t N = size_t(grid[0]) * grid[1] * grid[2];
   const size_t cplx = complex_buffer_bytes(grid[0], grid[1], grid[2], precision, nq);
-  return 2 * cplx + 4 * N * sizeof(double) + size_t(grid[1]) * (grid[2] / 2 + 1) * sizeof(double) + 64;
+  return 2 * cplx + 4 * N * sizeof(double) + N * state_bytes(precision) +
+         size_t(grid[1]) * (grid[2] / 2 + 1) * sizeof(double) + 64;
 }
 
 vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
@@ -735,11 +733,16 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   if ((e = hipMalloc(&h->d_A, h->buf_bytes)) != hipSuccess) return bail(e, "work buffer A");
   if ((e = hipMalloc(&h->d_B, h->buf_bytes)) != hipSuccess) return bail(e, "work buffer B");
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_S), N * sizeof(double))) != hipSuccess) return bail(e, "dE/dsigma buffer");
+  if ((e = hipMalloc(&h->d_state, N * state_bytes(precision))) != hipSuccess) return bail(e, "spline state buffer");
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_G), 3 * N * sizeof(double))) != hipSuccess) return bail(e, "gradient buffer");
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_partials), size_t(h->n2) * h->h3 * sizeof(double))) != hipSuccess)
     return bail(e, "energy partials");
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_energy), sizeof(double))) != hipSuccess) return bail(e, "energy");
-  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_flag), sizeof(int))) != hipSuccess) return bail(e, "flag");
+  // [0]: raised by the theta pass, [1]: the last evaluation's result (see k_energy_reduce)
+  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_flag), 2 * sizeof(int))) != hipSuccess) return bail(e, "flag");
+  if ((e = hipMemsetAsync(h->d_flag, 0, 2 * sizeof(int), h->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+    return bail(e, "flag");
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&h->h_energy), sizeof(double), hipHostMallocDefault)) != hipSuccess)
     return bail(e, "pinned energy");
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&h->h_flag), sizeof(int), hipHostMallocDefault)) != hipSuccess)
@@ -750,10 +753,8 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_theta_zfwd<double, kEPT, true>, h->lds_theta64);
   set_lds_limit(k_theta_zfwd<float, kEPT, false>, h->lds_theta32);
   set_lds_limit(k_theta_zfwd<float, kEPT, true>, h->lds_theta32);
-  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA, false>, h->lds_asm64);
-  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA, true>, h->lds_asm64);
-  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA, false>, h->lds_asm32);
-  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA, true>, h->lds_asm32);
+  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA>, h->lds_asm64);
+  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA>, h->lds_asm32);
   set_lds_limit(k_real_zfwd<double, kEPT, 0>, h->zl64.lds);
   set_lds_limit(k_real_zfwd<double, kEPT, 1>, h->zl64.lds);
   set_lds_limit(k_real_zfwd<float, kEPT, 1>, h->zl32.lds);

@@ -68,7 +68,7 @@ def _dispatches(path):
 def _per_stage(disp):
     """Assign library dispatches to stages in launch order; average over evaluations."""
     acc = collections.defaultdict(list)
-    lib = [(n, v) for n, v in disp if "vdwxc::" in n and "k_clear_flag" not in n]
+    lib = [(n, v) for n, v in disp if "vdwxc::" in n]
     i = 0
     while i < len(lib):
         for sym, stage in _STAGE_ORDER:

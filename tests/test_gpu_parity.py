@@ -235,6 +235,18 @@ def test_nan_input_is_rejected(dev):
     n[3, 4, 5] = 0.1
     E, _, _ = f.calculate(n, s)   # the handle stays usable
     assert math.isfinite(E)
+    # asynchronous entry: the device energy is NaN for that evaluation only
+    g = torch.zeros((3,) + grid, dtype=torch.float64, device=dev)
+    v = torch.empty_like(n)
+    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    n[1, 2, 3] = float("nan")
+    f.potential_async(n, g, v, e)
+    torch.cuda.synchronize()
+    assert math.isnan(float(e.item()))
+    n[1, 2, 3] = 0.1
+    f.potential_async(n, g, v, e)
+    torch.cuda.synchronize()
+    assert float(e.item()) == E
 
 
 def test_deterministic_bitwise(dev):
