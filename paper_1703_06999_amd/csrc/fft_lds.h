@@ -45,7 +45,7 @@ __host__ __device__ constexpr int lds_span(int n) {
   }
 }
 
-// Radix schedule of one transform length: radices 8, 4, 2, 3, 5, 7.  mnb[s] and mp[s] divide
+// Radix schedule of one transform length: radices 16, 8, 4, 2, 3, 5, 7.  mnb[s] and mp[s] divide
 // by n / radix[s] and by p_s (the product of the radices before stage s) without a division:
 // x / d = umulhi(x, ceil(2^32 / d)), exact whenever x d < 2^32 (here x < 2^14, d <= 2^11);
 // 0 encodes d = 1.
@@ -112,6 +112,42 @@ template <int DIR, typename T2> struct SmallDft<8, DIR, T2> {
     for (int k = 0; k < 4; ++k) {
       v[k] = cadd(e[k], o[k]);
       v[k + 4] = csub(e[k], o[k]);
+    }
+  }
+};
+
+// 16 = 4 x 4: DFT-4 over the four interleaved quarter sequences x[4a + b], twiddle by
+// exp(DIR 2 pi i b c / 16), then DFT-4 across b; output c + 4 d.
+template <int DIR, typename T2> struct SmallDft<16, DIR, T2> {
+  template <typename T>
+  __device__ __forceinline__ static T2 turn(T2 a, T c, T s) {   // a * (c + DIR i s)
+    return T2{c * a.x - DIR * s * a.y, c * a.y + DIR * s * a.x};
+  }
+  __device__ __forceinline__ static void run(T2* v) {
+    using T = decltype(v[0].x);
+    const T c1 = T(0.9238795325112867561281832), s1 = T(0.3826834323650897717284600);
+    const T h = T(0.7071067811865475244008444);
+    T2 y[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      y[b][0] = v[b]; y[b][1] = v[4 + b]; y[b][2] = v[8 + b]; y[b][3] = v[12 + b];
+      SmallDft<4, DIR, T2>::run(y[b]);
+    }
+    y[1][1] = turn(y[1][1], c1, s1);
+    y[1][2] = turn(y[1][2], h, h);
+    y[1][3] = turn(y[1][3], s1, c1);
+    y[2][1] = turn(y[2][1], h, h);
+    y[2][2] = rot90<DIR>(y[2][2]);
+    y[2][3] = turn(y[2][3], -h, h);
+    y[3][1] = turn(y[3][1], s1, c1);
+    y[3][2] = turn(y[3][2], -h, h);
+    y[3][3] = turn(y[3][3], -c1, -s1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      T2 z[4] = {y[0][c], y[1][c], y[2][c], y[3][c]};
+      SmallDft<4, DIR, T2>::run(z);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[c + 4 * d] = z[d];
     }
   }
 };
@@ -237,7 +273,7 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
 
 // Transform `nlines` LDS lines of length plan.n.  Requires nlines * n <= nthr * EPT.  The caller
 // must have synchronised after filling the lines; the lines are complete on return.  The plan
-// lists its radices grouped (all 8s, then 4, 2, 3s, 5s, 7s), so each radix runs in its own loop
+// lists its radices grouped (all 16s, then 8s, 4, 2, 3s, 5s, 7s), so each radix runs in its own loop
 // and the register allocation of one stage kind does not inflate the others.
 template <int R, int EPT, int DIR, int PS, typename T2>
 __device__ __forceinline__ void run_stages(T2* buf, const AxisPlan& plan, int n, int count, int& s0, int& p,
@@ -255,12 +291,13 @@ __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
   // keep the per-stage constants of this call from being hoisted into registers that stay live
   // across a caller's loop around the transform
   asm volatile("" : "+s"(n));
-  int cnt[6] = {0, 0, 0, 0, 0, 0};   // radix 8, 4, 2, 3, 5, 7
+  int cnt[7] = {0, 0, 0, 0, 0, 0, 0};   // radix 16, 8, 4, 2, 3, 5, 7
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.radix[s];
-    cnt[R == 8 ? 0 : R == 4 ? 1 : R == 2 ? 2 : R == 3 ? 3 : R == 5 ? 4 : 5] += 1;
+    cnt[R == 16 ? 6 : R == 8 ? 0 : R == 4 ? 1 : R == 2 ? 2 : R == 3 ? 3 : R == 5 ? 4 : 5] += 1;
   }
   int p = 1, s0 = 0;
+  run_stages<16, EPT, DIR, PS>(buf, plan, n, cnt[6], s0, p, nlines, lstride, tw, tid, nthr);
   run_stages<8, EPT, DIR, PS>(buf, plan, n, cnt[0], s0, p, nlines, lstride, tw, tid, nthr);
   run_stages<4, EPT, DIR, PS>(buf, plan, n, cnt[1], s0, p, nlines, lstride, tw, tid, nthr);
   run_stages<2, EPT, DIR, PS>(buf, plan, n, cnt[2], s0, p, nlines, lstride, tw, tid, nthr);

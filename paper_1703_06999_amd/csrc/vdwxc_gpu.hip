@@ -23,6 +23,9 @@ using namespace vdwxc;
 
 namespace {
 
+#ifndef VDWXC_RADIX16
+#define VDWXC_RADIX16 1
+#endif
 constexpr int kEPTA = 4;         // grid points (and FFT elements) per thread in the z assembly
 constexpr int kEPT = 8;          // FFT elements per thread in the z and y passes
 #ifndef VDWXC_EPTX
@@ -121,9 +124,18 @@ bool factor_axis(int n, AxisPlan& p) {
   p.n = n;
   p.nst = 0;
   int m = n;
-  while (m % 8 == 0 && p.nst < kMaxStages) { p.radix[p.nst++] = 8; m /= 8; }
-  if (m % 4 == 0) { p.radix[p.nst++] = 4; m /= 4; }
-  if (m % 2 == 0) { p.radix[p.nst++] = 2; m /= 2; }
+  // power-of-two part 2^e in ceil(e / 3) stages of 8 (then one 4 or 2), except that a 16 replaces
+  // an 8 where it saves a stage (2^7 = 16 * 8 rather than 8 * 8 * 2)
+  int e = 0;
+  while (m % 2 == 0) { m /= 2; ++e; }
+#if VDWXC_RADIX16
+  const int n16 = e % 3 == 1 && e >= 4 ? 1 : e % 3 == 2 && e >= 8 ? 2 : 0;
+#else
+  const int n16 = 0;
+#endif
+  for (int i = 0; i < n16; ++i) { p.radix[p.nst++] = 16; e -= 4; }
+  while (e >= 3) { p.radix[p.nst++] = 8; e -= 3; }
+  if (e > 0) p.radix[p.nst++] = 1 << e;
   for (int r : {3, 5, 7}) {
     while (m % r == 0) {
       if (p.nst >= kMaxStages) return false;

@@ -97,6 +97,10 @@ CASES = [
     ((1, 2, 2), 2.0, 6),
     ((5, 7, 3), 3.0, 7),
     ((2, 3, 1), 2.0, 8),
+    # radix-16 stages: 16, 48 = 16 * 3, 80 = 16 * 5, 256 = 16 * 16 and 128 = 16 * 8 on the x axis
+    ((16, 48, 80), 14.0, 9),
+    ((256, 9, 12), 40.0, 10),
+    ((128, 16, 10), 20.0, 11),
 ]
 
 
