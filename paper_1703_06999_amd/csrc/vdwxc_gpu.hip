@@ -277,6 +277,65 @@ size_t zstate_lds(const Launch& L, int n3, int per_point_values) {
   return L.lds + npts * per_point_values * sizeof(T) + ((npts + 15) & ~size_t(15)) + spline_lds_bytes<T>();
 }
 
+// Occupancy-driven z tile.  A z-pass block holds TILE lines plus TILE*n3 points of per-point state,
+// so its LDS and thread count scale with the tile; how many blocks then share a CU depends on that
+// and on the kernel's registers.  E.g. at n3 = 192 a 16-line theta block (6 waves, ~59 KB) leaves
+// two blocks (12 waves) per CU where 8-line blocks (3 waves, ~30 KB) fit five (15 waves).  The
+// largest tile whose resident waves per CU come within 10% of the best tile's wins: a block's
+// set-up (twiddles, spline tables) and its barriers are shared by more lines, which measured
+// worth more than the last wave or two (n3 = 192: 15 waves at 8 lines beat 16 waves at 4).
+// Blocks of one wave are not considered unless no larger block fits.
+bool zline_config(int tile, int n3, size_t cplx_bytes, int ept, Launch& L) {
+  if (long(tile) * n3 > long(kMaxThreadsZ) * ept || n3 > kMaxAxis) return false;
+  L.tile = tile;
+  L.nthr = threads_for(long(tile) * n3, ept, kMaxThreadsZ);
+  L.lstride = lds_span<>(n3) | 1;
+  L.lds = ((size_t(n3) * cplx_bytes + 15) & ~size_t(15)) + size_t(tile) * L.lstride * cplx_bytes;
+  return true;
+}
+
+template <typename K>
+int resident_waves(K* kernel, int nthr, size_t lds) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void*>(kernel), nthr, lds) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return blocks * ((nthr + 63) / 64);
+}
+
+// `values` per-point values of type T sit next to the lines (zstate_lds); false if no tile fits.
+// On success `out` is the launch and `lds_out` its total LDS.
+template <typename T, typename K>
+bool pick_ztile(K* kernel, int n3, int other, int values, int ept, Launch& out, size_t& lds_out) {
+  struct Cand {
+    Launch L;
+    size_t lds;
+    int waves;
+  };
+  Cand c[8];
+  int nc = 0, best = 0;
+  for (int tile = std::min(kLineTile, std::max(1, other)); tile >= 1 && nc < 8; tile /= 2) {
+    Launch L;
+    if (!zline_config(tile, n3, 2 * sizeof(T), ept, L)) continue;
+    // one-wave blocks only where nothing larger fits: their per-block set-up is not repaid
+    if (nc > 0 && L.nthr < 128) break;
+    const size_t lds = zstate_lds<T>(L, n3, values);
+    if (lds > kMaxLds) continue;
+    c[nc] = Cand{L, lds, resident_waves(kernel, L.nthr, lds)};
+    best = std::max(best, c[nc].waves);
+    ++nc;
+  }
+  for (int i = 0; i < nc; ++i)   // candidates run from the largest tile down
+    if (10 * c[i].waves >= 9 * best) {
+      out = c[i].L;
+      lds_out = c[i].lds;
+      return true;
+    }
+  return false;
+}
+
 // bytes per grid point of the spline state passed from the theta pass to the assembly
 size_t state_bytes(vdwxc_precision p) { return p == VDWXC_FP64 ? sizeof(Quad<double>) : sizeof(Quad<float>); }
 
@@ -759,6 +818,19 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     return bail(e, "pinned energy");
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&h->h_flag), sizeof(int), hipHostMallocDefault)) != hipSuccess)
     return bail(e, "pinned flag");
+
+  // z tiles by occupancy (the plain-field z passes share the theta tile)
+  set_lds_limit(k_theta_zfwd<double, kEPT, true>, kMaxLds);
+  set_lds_limit(k_theta_zfwd<float, kEPT, true>, kMaxLds);
+  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA>, kMaxLds);
+  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA>, kMaxLds);
+  if (!pick_ztile<double>(k_theta_zfwd<double, kEPT, true>, h->n3, h->n2, 2, kEPT, h->zl64, h->lds_theta64) ||
+      !pick_ztile<float>(k_theta_zfwd<float, kEPT, true>, h->n3, h->n2, 2, kEPT, h->zl32, h->lds_theta32) ||
+      !pick_ztile<double>(k_zinv_assemble<double, kEPTA, kEPTA>, h->n3, h->n2, 3, kEPTA, h->za64, h->lds_asm64) ||
+      !pick_ztile<float>(k_zinv_assemble<float, kEPTA, kEPTA>, h->n3, h->n2, 3, kEPTA, h->za32, h->lds_asm32)) {
+    release(h);
+    return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
+  }
 
   // dynamic LDS above the default limit
   set_lds_limit(k_theta_zfwd<double, kEPT, false>, h->lds_theta64);
