@@ -57,6 +57,7 @@ def stage_bytes(stage: str, grid, precision: str, m: int = M) -> float:
     N = n1 * n2 * n3
     Nk = n1 * n2 * (n3 // 2 + 1)
     c = 16 if precision == "fp64" else 8          # complex element
+    r = c // 2                                    # real element
     st = 32 if precision == "fp64" else 16        # per-point spline state, theta pass -> assembly
     return {
         "theta_zfwd": 32 * N + m * Nk * c + st * N,   # n + grad in, theta(kz) and state out
@@ -65,11 +66,9 @@ def stage_bytes(stage: str, grid, precision: str, m: int = M) -> float:
         "y_inv": 2 * m * Nk * c,
         "z_assemble": m * Nk * c + st * N + 16 * N,   # F(kz), state in; v, dE/dsigma out
         "energy": 8 * n2 * (n3 // 2 + 1),
-        "div_z": 32 * N + 3 * Nk * c,
-        "div_y": 2 * 3 * Nk * c,
-        "div_x": 4 * Nk * c,
-        "div_yi": 2 * Nk * c,
-        "div_zi": Nk * c + 16 * N,
+        "div_z": 32 * N + 3 * r * N,                  # S + grad in; A, B1, B2 out
+        "div_y": 5 * r * N,                            # A, B1, B2 in; A', B1' out
+        "div_x": 2 * r * N + 16 * N,                   # A', B1' and v in; v out
     }.get(stage, 0.0)
 
 

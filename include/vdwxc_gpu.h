@@ -133,12 +133,10 @@ typedef enum {
   VDWXC_STAGE_GRAD_X = 8,
   VDWXC_STAGE_GRAD_YI = 9,
   VDWXC_STAGE_GRAD_ZI = 10,
-  VDWXC_STAGE_DIV_Z = 11,       /* spectral divergence of 2 dE/dsigma grad n: z, y, x, y, z passes */
-  VDWXC_STAGE_DIV_Y = 12,
+  VDWXC_STAGE_DIV_Z = 11,       /* spectral divergence of 2 dE/dsigma grad n, one axis per pass: */
+  VDWXC_STAGE_DIV_Y = 12,       /* z, y, x (the x pass subtracts it from the potential) */
   VDWXC_STAGE_DIV_X = 13,
-  VDWXC_STAGE_DIV_YI = 14,
-  VDWXC_STAGE_DIV_ZI = 15,
-  VDWXC_NUM_STAGES = 16
+  VDWXC_NUM_STAGES = 14
 } vdwxc_stage;
 
 /* Per-stage timing with HIP events recorded on the handle's stream around every kernel launch

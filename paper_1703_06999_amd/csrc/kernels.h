@@ -426,15 +426,13 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
   }
 }
 
-// ---- pass 1 for plain real fields (spectral gradient / divergence inputs) --------------------
-// MODE 0: nf fields read from src[f*N + idx].  MODE 1: the three fields 2*S*g_c (divergence
-// input), S = dE/dsigma (src) and g the gradient (aux, [3][N]).
+// ---- pass 1 for plain real fields (spectral gradient input) ---------------------------------
+// nf FP64 fields read from src[f*N + idx], transformed in pairs (one complex line per two fields).
 
-template <typename T, int EPT, int MODE>
+template <typename T, int EPT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_REALZ)))
-k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int nf,
-            typename Cx<T>::type* __restrict__ A, const typename Cx<T>::type* __restrict__ tw,
-            Geometry g, AxisPlan zp, int ty, int lstride) {
+k_real_zfwd(const double* __restrict__ src, int nf, typename Cx<T>::type* __restrict__ A,
+            const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
@@ -451,26 +449,21 @@ k_real_zfwd(const double* __restrict__ src, const double* __restrict__ aux, int 
   for (int fa = 0; fa < nf; fa += 2) {
     const int fb = fa + 1;
     struct Raw {
-      double a, b, s;
+      double a, b;
     };
     gather_strided_dm<4>(
         tid, nthr, npts, n3,
         [&](int, int yl, int z) {
           const int y = y0 + yl;
-          Raw r{0.0, 0.0, 0.0};
+          Raw r{0.0, 0.0};
           if (y < g.n2) {
             const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-            const double* f = MODE == 0 ? src : aux;
-            r.a = f[size_t(fa) * N + idx];
-            if (fb < nf) r.b = f[size_t(fb) * N + idx];
-            if (MODE == 1) r.s = src[idx];
+            r.a = src[size_t(fa) * N + idx];
+            if (fb < nf) r.b = src[size_t(fb) * N + idx];
           }
           return r;
         },
-        [&](int, int yl, int z, const Raw& r) {
-          const double s2 = MODE == 0 ? 1.0 : 2.0 * r.s;
-          line[yl * lstride + lidx<>(z)] = T2{T(s2 * r.a), T(s2 * r.b)};
-        });
+        [&](int, int yl, int z, const Raw& r) { line[yl * lstride + lidx<>(z)] = T2{T(r.a), T(r.b)}; });
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
     const int nout = ty * g.h3;
@@ -787,13 +780,14 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
   }
 }
 
-// ---- pass 3 for the spectral gradient (1 -> 3 fields) and divergence (3 -> 1) ----------------
+// ---- pass 3 for the spectral gradient (1 -> 3 fields) ----------------------------------------
 // D_c f = IFFT(i G_c FFT f) with every frequency touching a Nyquist index set to zero.
 
-template <typename T, int EPT, int NIN, int NOUT>
+template <typename T, int EPT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_XS)))
-k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ tw,
+k_xgradient(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ tw,
             Geometry g, AxisPlan xp) {
+  constexpr int NIN = 1, NOUT = 3;
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n1);
@@ -818,24 +812,11 @@ k_xspectral(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __
     double G[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) G[c] = fx * g.bvec[c] + fy * g.bvec[3 + c] + fz * g.bvec[6 + c];
-    T2 in[NIN];
+    const T2 in = line[lidx<>(kx)];
 #pragma unroll
-    for (int f = 0; f < NIN; ++f) in[f] = line[f * ls + lidx<>(kx)];
-    if (NIN == 1) {
-#pragma unroll
-      for (int c = 0; c < NOUT; ++c) {   // i G_c X
-        const T gc = zero ? T(0) : T(G[c]);
-        line[c * ls + lidx<>(kx)] = T2{-gc * in[0].y, gc * in[0].x};
-      }
-    } else {
-      T2 acc = T2{T(0), T(0)};
-#pragma unroll
-      for (int c = 0; c < NIN; ++c) {    // sum_c i G_c X_c
-        const T gc = zero ? T(0) : T(G[c]);
-        acc.x -= gc * in[c].y;
-        acc.y += gc * in[c].x;
-      }
-      line[lidx<>(kx)] = acc;
+    for (int c = 0; c < NOUT; ++c) {   // i G_c X
+      const T gc = zero ? T(0) : T(G[c]);
+      line[c * ls + lidx<>(kx)] = T2{-gc * in.y, gc * in.x};
     }
   }
   __syncthreads();
@@ -1044,9 +1025,9 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __res
   }
 }
 
-// ---- pass 5 for plain real fields: out[f] = IFFT/N (COMBINE: out[0] -= IFFT/N) -------------
+// ---- pass 5 for plain real fields: out[f] = IFFT/N ---------------------------------------------
 
-template <typename T, int EPT, bool COMBINE>
+template <typename T, int EPT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_REALZI)))
 k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restrict__ out,
             const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
@@ -1069,28 +1050,269 @@ k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restri
     load_pair_line(A, g, fa, fb, x, y0, ty, line, lstride, tid, nthr);
     __syncthreads();
     lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
-    // COMBINE reads the previous output; gathered so that those loads are in flight together
-    gather_strided_dm<8>(
-        tid, nthr, npts, n3,
-        [&](int, int yl, int z) {
-          const int y = y0 + yl;
-          return (COMBINE && y < g.n2) ? out[(size_t(x) * g.n2 + y) * n3 + z] : 0.0;
-        },
-        [&](int, int yl, int z, double old) {
-          const int y = y0 + yl;
-          if (y < g.n2) {
-            const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-            const T2 v = line[yl * lstride + lidx<>(z)];
-            if (COMBINE) {
-              out[idx] = old - double(v.x) * invN;
-            } else {
-              out[size_t(fa) * N + idx] = double(v.x) * invN;
-              if (fb >= 0) out[size_t(fb) * N + idx] = double(v.y) * invN;
-            }
-          }
-        });
+    DivModStep it(tid, nthr, n3);
+    for (int e = tid; e < npts; e += nthr, it.next()) {
+      const int yl = it.q, z = it.r, y = y0 + yl;
+      if (y < g.n2) {
+        const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
+        const T2 v = line[yl * lstride + lidx<>(z)];
+        out[size_t(fa) * N + idx] = double(v.x) * invN;
+        if (fb >= 0) out[size_t(fb) * N + idx] = double(v.y) * invN;
+      }
+    }
     __syncthreads();
   }
+}
+
+// ---- spectral divergence, one axis at a time ---------------------------------------------------
+// The divergence of h_c = 2 (dE/dsigma) g_c is (1/N) F^-1 [chi(m) sum_c i G_c F h_c] with G the
+// wave vector of index m and chi zero wherever an index is a Nyquist index.  With G = sum_i m_i b_i
+// (b_i the reciprocal vectors, m_i the signed indices), sum_c G_c h^_c = sum_i m_i H^_i for the
+// real-space combinations H_i = sum_c b_i,c h_c, and chi = chi_1 chi_2 chi_3 factors over the axes.
+// So the operator splits into one-dimensional ones along each axis of length n:
+//   D = (1/n) F^-1 [i m chi(m)] F   (spectral derivative in index units, Nyquist dropped)
+//   P = (1/n) F^-1 chi F            (removal of the Nyquist mode (-1)^x: an alternating sum;
+//                                    the identity for odd n)
+// and div = P_y P_z D_x H_1 + P_x P_z D_y H_2 + P_x P_y D_z H_3.  P_a commutes with D_b (b != a)
+// and P_a D_a = D_a, which gives three line passes:
+//   z: A = D_z H_3,            B1 = P_z H_1,  B2 = P_z H_2
+//   y: A' = P_y A + D_y B2,    B1' = P_y B1
+//   x: div = P_x A' + D_x B1'
+// This is the same linear operator as the three-dimensional transform, with one derivative FFT
+// pair per point and pass instead of forward transforms of three fields and an inverse of one.
+// Each pass keeps whole lines of its axis in LDS: "P lines" (two real series as re/im of one
+// complex line) get the projection, "D lines" (two real series packed the same way) the derivative
+// through one forward and one inverse complex FFT.  The multiplier i m chi / n maps real series to
+// real series, so the packed pair comes back as (D a, D b).
+
+// loads in flight per thread in the divergence passes: each block streams its whole tile once,
+// and one block per CU slot covers the grid at typical sizes, so the load latency is not hidden
+// by other blocks
+#ifndef VDWXC_DIV_U
+#define VDWXC_DIV_U 8
+#endif
+constexpr int kDivU = VDWXC_DIV_U;
+
+// np P lines and nd D lines of length plan.n in LDS (stride lstride).  On return the D lines hold
+// their derivatives and csum[l] = (1/n) sum_x (-1)^x P_l[x] (zero for odd n); the caller subtracts
+// (-1)^x csum[l] from P line l.  Requires nd * n <= nthr * EPT, nthr a multiple of 64, and the
+// lines complete (synchronised) on entry; lines and csum are complete on return.
+template <int EPT, typename T2>
+__device__ __forceinline__ void project_and_derive(T2* pl, int np, T2* dl, int nd, T2* csum, int lstride,
+                                                   const AxisPlan& plan, const T2* __restrict__ tw, int tid,
+                                                   int nthr) {
+  using T = decltype(pl[0].x);
+  const int n = plan.n;
+  const T invn = T(1) / T(n);
+  if ((n & 1) == 0) {
+    // one wave per P line: strided alternating partial sums, then a butterfly over the lanes
+    const int lane = tid & 63, nwave = nthr >> 6;
+    for (int l = tid >> 6; l < np; l += nwave) {
+      T sx = T(0), sy = T(0);
+      for (int i = lane; i < n; i += 64) {
+        const T2 v = pl[l * lstride + lidx<>(i)];
+        const T sg = (i & 1) ? T(-1) : T(1);
+        sx += sg * v.x;
+        sy += sg * v.y;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_xor(sx, off, 64);
+        sy += __shfl_xor(sy, off, 64);
+      }
+      if (lane == 0) csum[l] = T2{sx * invn, sy * invn};
+    }
+  } else {
+    for (int l = tid; l < np; l += nthr) csum[l] = T2{T(0), T(0)};
+  }
+  if (nd > 0) {
+    lds_fft<EPT, -1>(dl, plan, nd, lstride, tw, tid, nthr);
+    DivModStep it(tid, nthr, n);
+    for (int e = tid; e < nd * n; e += nthr, it.next()) {
+      const int l = it.q, m = it.r;
+      const T mu = is_nyquist(m, n) ? T(0) : T(signed_freq(m, n)) * invn;
+      T2& v = dl[l * lstride + lidx<>(m)];
+      v = T2{-mu * v.y, mu * v.x};
+    }
+    __syncthreads();
+    lds_fft<EPT, +1>(dl, plan, nd, lstride, tw, tid, nthr);
+  } else {
+    __syncthreads();
+  }
+}
+
+// z pass.  Block: `ty` y lines of one x plane (the z-pass block order).  in: S = dE/dsigma and the
+// three gradient components; out: [A, B1, B2] as three real fields of N points (natural order).
+template <typename T, int EPT>
+__global__ void __launch_bounds__(512)
+k_div_z(const double* __restrict__ S, const double* __restrict__ grad, T* __restrict__ out,
+        const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
+  using T2 = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  int tile, x;
+  zpass_block(tile, x);
+  const int y0 = tile * ty, n3 = g.n3;
+  const size_t N = size_t(g.n1) * g.n2 * n3;
+  const int nd = (ty + 1) >> 1, npts = ty * n3;
+  T2* pl = reinterpret_cast<T2*>(smem);     // line yl: (H_1, H_2)
+  T2* dl = pl + size_t(ty) * lstride;        // line j: (H_3 of yl = 2j, 2j+1)
+  T2* csum = dl + size_t(nd) * lstride;
+  struct In {
+    double s, g0, g1, g2;
+  };
+  gather_strided_dm<kDivU>(
+      tid, nthr, npts, n3,
+      [&](int, int yl, int z) {
+        const int y = y0 + yl;
+        In r{0.0, 0.0, 0.0, 0.0};
+        if (y < g.n2) {
+          const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
+          r.s = S[idx];
+          r.g0 = grad[idx];
+          r.g1 = grad[N + idx];
+          r.g2 = grad[2 * N + idx];
+        }
+        return r;
+      },
+      [&](int, int yl, int z, const In& r) {
+        const double s2 = 2.0 * r.s;
+        double H[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) H[i] = s2 * (g.bvec[3 * i] * r.g0 + g.bvec[3 * i + 1] * r.g1 + g.bvec[3 * i + 2] * r.g2);
+        pl[yl * lstride + lidx<>(z)] = T2{T(H[0]), T(H[1])};
+        T* d = reinterpret_cast<T*>(dl + (yl >> 1) * lstride + lidx<>(z));
+        d[yl & 1] = T(H[2]);
+        if (!(yl & 1) && yl + 1 == ty) d[1] = T(0);   // odd tile: the last pair has one member
+      });
+  __syncthreads();
+  project_and_derive<EPT>(pl, ty, dl, nd, csum, lstride, zp, twl, tid, nthr);
+  DivModStep it(tid, nthr, n3);
+  for (int e = tid; e < npts; e += nthr, it.next()) {
+    const int yl = it.q, z = it.r, y = y0 + yl;
+    if (y < g.n2) {
+      const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
+      const T2 p = pl[yl * lstride + lidx<>(z)], c = csum[yl];
+      const T2 d = dl[(yl >> 1) * lstride + lidx<>(z)];
+      const T sg = (z & 1) ? T(-1) : T(1);
+      out[idx] = (yl & 1) ? d.y : d.x;
+      out[N + idx] = p.x - sg * c.x;
+      out[2 * N + idx] = p.y - sg * c.y;
+    }
+  }
+}
+
+// y pass.  Block: `tz` consecutive z of one x plane (grid: z tiles x n1, XCD-aware order, so the
+// blocks that share the cache lines of a row run on one XCD).  in: [A, B1, B2]; out: [A', B1'].
+template <typename T, int EPT>
+__global__ void __launch_bounds__(512)
+k_div_y(const T* __restrict__ in, T* __restrict__ out, const typename Cx<T>::type* __restrict__ tw, Geometry g,
+        AxisPlan yp, int tz, int lstride) {
+  using T2 = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n2);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n2, threadIdx.x, blockDim.x);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = xcd_logical_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int z0 = (L % gridDim.x) * tz, x = L / gridDim.x;
+  const int n2 = g.n2, n3 = g.n3;
+  const size_t N = size_t(g.n1) * n2 * n3;
+  const int nd = (tz + 1) >> 1, tot = tz * n2;
+  T2* pl = reinterpret_cast<T2*>(smem);     // line zl: (A, B1)
+  T2* dl = pl + size_t(tz) * lstride;        // line j: (B2 of zl = 2j, 2j+1)
+  T2* csum = dl + size_t(nd) * lstride;
+  struct In {
+    T a, b1, b2;
+  };
+  gather_strided_dm<kDivU>(
+      tid, nthr, tot, tz,
+      [&](int, int y, int zl) {
+        In r{T(0), T(0), T(0)};
+        if (z0 + zl < n3) {
+          const size_t idx = (size_t(x) * n2 + y) * n3 + z0 + zl;
+          r.a = in[idx];
+          r.b1 = in[N + idx];
+          r.b2 = in[2 * N + idx];
+        }
+        return r;
+      },
+      [&](int, int y, int zl, const In& r) {
+        pl[zl * lstride + lidx<>(y)] = T2{r.a, r.b1};
+        T* d = reinterpret_cast<T*>(dl + (zl >> 1) * lstride + lidx<>(y));
+        d[zl & 1] = r.b2;
+        if (!(zl & 1) && zl + 1 == tz) d[1] = T(0);
+      });
+  __syncthreads();
+  project_and_derive<EPT>(pl, tz, dl, nd, csum, lstride, yp, twl, tid, nthr);
+  DivModStep it(tid, nthr, tz);
+  for (int e = tid; e < tot; e += nthr, it.next()) {
+    const int y = it.q, zl = it.r;
+    if (z0 + zl < n3) {
+      const size_t idx = (size_t(x) * n2 + y) * n3 + z0 + zl;
+      const T2 p = pl[zl * lstride + lidx<>(y)], c = csum[zl];
+      const T2 d = dl[(zl >> 1) * lstride + lidx<>(y)];
+      const T sg = (y & 1) ? T(-1) : T(1);
+      out[idx] = (p.x - sg * c.x) + ((zl & 1) ? d.y : d.x);
+      out[N + idx] = p.y - sg * c.y;
+    }
+  }
+}
+
+// x pass.  Block: `tz` consecutive z of one y (grid: z tiles x n2, XCD-aware order).  in: [A', B1'];
+// v -= P_x A' + D_x B1'.
+template <typename T, int EPT>
+__global__ void __launch_bounds__(512)
+k_div_x(const T* __restrict__ in, double* __restrict__ v, const typename Cx<T>::type* __restrict__ tw, Geometry g,
+        AxisPlan xp, int tz, int lstride) {
+  using T2 = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n1);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n1, threadIdx.x, blockDim.x);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = xcd_logical_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int z0 = (L % gridDim.x) * tz, y = L / gridDim.x;
+  const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
+  const size_t N = size_t(n1) * n2 * n3;
+  const int nd = (tz + 1) >> 1, tot = tz * n1;
+  T2* pl = reinterpret_cast<T2*>(smem);     // line j: (A' of zl = 2j, 2j+1)
+  T2* dl = pl + size_t(nd) * lstride;        // line j: (B1' of zl = 2j, 2j+1)
+  T2* csum = dl + size_t(nd) * lstride;
+  struct In {
+    T a, b;
+  };
+  gather_strided_dm<kDivU>(
+      tid, nthr, tot, tz,
+      [&](int, int x, int zl) {
+        In r{T(0), T(0)};
+        if (z0 + zl < n3) {
+          const size_t idx = (size_t(x) * n2 + y) * n3 + z0 + zl;
+          r.a = in[idx];
+          r.b = in[N + idx];
+        }
+        return r;
+      },
+      [&](int, int x, int zl, const In& r) {
+        T* p = reinterpret_cast<T*>(pl + (zl >> 1) * lstride + lidx<>(x));
+        T* d = reinterpret_cast<T*>(dl + (zl >> 1) * lstride + lidx<>(x));
+        p[zl & 1] = r.a;
+        d[zl & 1] = r.b;
+        if (!(zl & 1) && zl + 1 == tz) p[1] = d[1] = T(0);
+      });
+  __syncthreads();
+  project_and_derive<EPT>(pl, nd, dl, nd, csum, lstride, xp, twl, tid, nthr);
+  gather_strided_dm<kDivU>(
+      tid, nthr, tot, tz,
+      [&](int, int x, int zl) { return z0 + zl < n3 ? v[(size_t(x) * n2 + y) * n3 + z0 + zl] : 0.0; },
+      [&](int, int x, int zl, double old) {
+        if (z0 + zl < n3) {
+          const T2 p = pl[(zl >> 1) * lstride + lidx<>(x)], c = csum[zl >> 1];
+          const T2 d = dl[(zl >> 1) * lstride + lidx<>(x)];
+          const T sg = (x & 1) ? T(-1) : T(1);
+          const T div = (zl & 1) ? (p.y - sg * c.y) + d.y : (p.x - sg * c.x) + d.x;
+          v[(size_t(x) * n2 + y) * n3 + z0 + zl] = old - double(div);
+        }
+      });
 }
 
 // ---- energy: fixed-order sum of the per-column partials --------------------------------------

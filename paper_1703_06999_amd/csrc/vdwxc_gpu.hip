@@ -26,6 +26,9 @@ namespace {
 #ifndef VDWXC_RADIX16
 #define VDWXC_RADIX16 1
 #endif
+#ifndef VDWXC_DIV_ZT
+#define VDWXC_DIV_ZT 16
+#endif
 constexpr int kEPTA = 4;         // grid points (and FFT elements) per thread in the z assembly
 constexpr int kEPT = 8;          // FFT elements per thread in the z and y passes
 #ifndef VDWXC_EPTX
@@ -72,7 +75,8 @@ struct vdwxc_ctx {
   int device = 0;
   Geometry geo{};
   AxisPlan plan[3]{};
-  Launch zl64, zl32, za64, za32, yl64, yl32, xl64, xl32, xs64, xs32;
+  Launch zl64, zl32, za64, za32, yl64, yl32, xl64, xl32, xs64;   // xs: gradient x pass (FP64)
+  Launch dz64, dz32, dy64, dy32, dx64, dx32;   // divergence passes (lds: the whole block)
   size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
   bool x_capped = false;   // launch the register-capped contraction kernel
   bool ortho = false;
@@ -305,17 +309,31 @@ int resident_waves(K* kernel, int nthr, size_t lds) {
   return blocks * ((nthr + 63) / 64);
 }
 
-// `values` per-point values of type T sit next to the lines (zstate_lds); false if no tile fits.
-// On success `out` is the launch and `lds_out` its total LDS.
+struct Cand {
+  Launch L;   // L.lds: the lines and twiddles
+  size_t lds; // the block's whole dynamic LDS
+};
+
+// The rule above over candidates listed from the largest tile down.
+template <typename K>
+bool pick_occupancy(K* kernel, const Cand* c, int nc, Launch& out, size_t& lds_out) {
+  int waves[8] = {0}, best = 0;
+  for (int i = 0; i < nc; ++i) best = std::max(best, waves[i] = resident_waves(kernel, c[i].L.nthr, c[i].lds));
+  for (int i = 0; i < nc; ++i)
+    if (10 * waves[i] >= 9 * best) {
+      out = c[i].L;
+      lds_out = c[i].lds;
+      return true;
+    }
+  return false;
+}
+
+// z passes with per-point state: `values` values of type T per point sit next to the lines
+// (zstate_lds).  Tiles halve from min(kLineTile, other).
 template <typename T, typename K>
 bool pick_ztile(K* kernel, int n3, int other, int values, int ept, Launch& out, size_t& lds_out) {
-  struct Cand {
-    Launch L;
-    size_t lds;
-    int waves;
-  };
   Cand c[8];
-  int nc = 0, best = 0;
+  int nc = 0;
   for (int tile = std::min(kLineTile, std::max(1, other)); tile >= 1 && nc < 8; tile /= 2) {
     Launch L;
     if (!zline_config(tile, n3, 2 * sizeof(T), ept, L)) continue;
@@ -323,17 +341,38 @@ bool pick_ztile(K* kernel, int n3, int other, int values, int ept, Launch& out, 
     if (nc > 0 && L.nthr < 128) break;
     const size_t lds = zstate_lds<T>(L, n3, values);
     if (lds > kMaxLds) continue;
-    c[nc] = Cand{L, lds, resident_waves(kernel, L.nthr, lds)};
-    best = std::max(best, c[nc].waves);
-    ++nc;
+    c[nc++] = Cand{L, lds};
   }
-  for (int i = 0; i < nc; ++i)   // candidates run from the largest tile down
-    if (10 * c[i].waves >= 9 * best) {
-      out = c[i].L;
-      lds_out = c[i].lds;
-      return true;
-    }
-  return false;
+  return pick_occupancy(kernel, c, nc, out, lds_out);
+}
+
+// Divergence passes (k_div_z / _y / _x): `tile` lines of the axis (length n) per block, held as
+// plines "P lines" and dlines "D lines" (complex, two real series each) plus one complex sum per
+// P line.  The z pass tiles y lines like the other z passes (tiles halve from min(kLineTile,
+// n2)); the y and x passes tile z in powers of two from min(16, n3 rounded up), at least 2.  The
+// chosen launch's L.lds is the block's whole LDS.
+int div_plines(int axis, int tile) { return axis == 0 ? (tile + 1) / 2 : tile; }
+
+template <typename T, typename K>
+bool pick_div(K* kernel, int axis, int n, int first_tile, Launch& out) {
+  const size_t cplx = 2 * sizeof(T);
+  Cand c[8];
+  int nc = 0;
+  const int last = axis == 2 ? 1 : 2;
+  for (int tile = first_tile; tile >= last && nc < 8; tile /= 2) {
+    const int np = div_plines(axis, tile), nd = (tile + 1) / 2;
+    if (long(nd) * n > long(kMaxThreadsZ) * kEPT || n > kMaxAxis) continue;
+    Launch L;
+    L.tile = tile;
+    L.nthr = threads_for(long(std::max(np, nd)) * n, kEPT, kMaxThreadsZ);
+    if (nc > 0 && L.nthr < 128) break;
+    L.lstride = lds_span<>(n) | 1;
+    L.lds = tw_lds_bytes<typename Cx<T>::type>(n) + size_t(np + nd) * L.lstride * cplx + size_t(np) * cplx;
+    if (L.lds > kMaxLds) continue;
+    c[nc++] = Cand{L, L.lds};
+  }
+  size_t lds = 0;
+  return pick_occupancy(kernel, c, nc, out, lds);
 }
 
 // bytes per grid point of the spline state passed from the theta pass to the assembly
@@ -396,6 +435,7 @@ template <> struct Prec<double> {
   static const Launch& y(const vdwxc_ctx* h) { return h->yl64; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& xs(const vdwxc_ctx* h) { return h->xs64; }
+  static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz64 : a == 1 ? h->dy64 : h->dx64; }
   static const double2* tw(const vdwxc_ctx* h, int a) { return h->d_tw64[a]; }
   static const Quad<double>* table(const vdwxc_ctx* h) { return h->d_table64; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta64; }
@@ -406,7 +446,7 @@ template <> struct Prec<float> {
   static const Launch& za(const vdwxc_ctx* h) { return h->za32; }
   static const Launch& y(const vdwxc_ctx* h) { return h->yl32; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
-  static const Launch& xs(const vdwxc_ctx* h) { return h->xs32; }
+  static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz32 : a == 1 ? h->dy32 : h->dx32; }
   static const float2* tw(const vdwxc_ctx* h, int a) { return h->d_tw32[a]; }
   static const Quad<float>* table(const vdwxc_ctx* h) { return h->d_table32; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta32; }
@@ -456,47 +496,55 @@ void enqueue_ypass(vdwxc_ctx* h, int nf, int dir, int stage) {
   stage_end(h, stage);
 }
 
-// forward FFT of nf real FP64 fields (MODE 0) or of 2 S g_c (MODE 1), through z, y, x; then the
-// x-pass spectral operator (1 -> 3 gradient or 3 -> 1 divergence), inverse x, y, and z into out
+// spectral gradient of the FP64 density n: forward z, y, x; i G_c on the x pass (1 -> 3 fields);
+// inverse x, y, z into out[3][N]
 template <typename T>
-void enqueue_spectral(vdwxc_ctx* h, int mode, const double* src, const double* aux, int nin, int nout,
-                      double* out) {
+void enqueue_gradient(vdwxc_ctx* h, const double* src, double* out) {
   using T2 = typename Cx<T>::type;
   const Launch& Lz = Prec<T>::z(h);
   const Launch& Lx = Prec<T>::xs(h);
   T2* A = static_cast<T2*>(h->d_A);
   T2* B = static_cast<T2*>(h->d_B);
   Geometry g = h->geo;
-  g.M = nin;
+  g.M = 1;
   dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
-  const int s0 = mode == 0 ? VDWXC_STAGE_GRAD_Z : VDWXC_STAGE_DIV_Z;
   stage_begin(h);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_real_zfwd<T, kEPT, 0>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, src, aux, nin, A,
-                       Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
-  else
-    hipLaunchKernelGGL((k_real_zfwd<T, kEPT, 1>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, src, aux, nin, A,
-                       Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
-  stage_end(h, s0);
-  enqueue_ypass<T>(h, nin, -1, s0 + 1);
-  dim3 xgrid(h->h3, h->n2);
+  hipLaunchKernelGGL((k_real_zfwd<T, kEPT>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, src, 1, A, Prec<T>::tw(h, 2),
+                     g, h->plan[2], Lz.tile, Lz.lstride);
+  stage_end(h, VDWXC_STAGE_GRAD_Z);
+  enqueue_ypass<T>(h, 1, -1, VDWXC_STAGE_GRAD_Y);
   stage_begin(h);
-  if (nin == 1)
-    hipLaunchKernelGGL((k_xspectral<T, kEPTX, 1, 3>), xgrid, dim3(Lx.nthr), Lx.lds, h->stream, B,
-                       Prec<T>::tw(h, 0), g, h->plan[0]);
-  else
-    hipLaunchKernelGGL((k_xspectral<T, kEPTX, 3, 1>), xgrid, dim3(Lx.nthr), Lx.lds, h->stream, B,
-                       Prec<T>::tw(h, 0), g, h->plan[0]);
-  stage_end(h, s0 + 2);
-  enqueue_ypass<T>(h, nout, +1, s0 + 3);
+  hipLaunchKernelGGL((k_xgradient<T, kEPTX>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
+                     Prec<T>::tw(h, 0), g, h->plan[0]);
+  stage_end(h, VDWXC_STAGE_GRAD_X);
+  enqueue_ypass<T>(h, 3, +1, VDWXC_STAGE_GRAD_YI);
   stage_begin(h);
-  if (nout == 3)
-    hipLaunchKernelGGL((k_real_zinv<T, kEPT, false>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, nout, out,
-                       Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
-  else
-    hipLaunchKernelGGL((k_real_zinv<T, kEPT, true>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, nout, out,
-                       Prec<T>::tw(h, 2), g, h->plan[2], Lz.tile, Lz.lstride);
-  stage_end(h, s0 + 4);
+  hipLaunchKernelGGL((k_real_zinv<T, kEPT>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, 3, out, Prec<T>::tw(h, 2),
+                     g, h->plan[2], Lz.tile, Lz.lstride);
+  stage_end(h, VDWXC_STAGE_GRAD_ZI);
+}
+
+// v -= spectral divergence of 2 S grad n, one axis at a time (k_div_z, k_div_y, k_div_x); the
+// intermediate real fields sit in the work buffers ([3][N] in A, [2][N] in B)
+template <typename T>
+void enqueue_divergence(vdwxc_ctx* h, const double* S, const double* grad, double* v) {
+  const Launch& Lz = Prec<T>::div(h, 2);
+  const Launch& Ly = Prec<T>::div(h, 1);
+  const Launch& Lx = Prec<T>::div(h, 0);
+  T* F3 = static_cast<T*>(h->d_A);
+  T* F2 = static_cast<T*>(h->d_B);
+  stage_begin(h);
+  hipLaunchKernelGGL((k_div_z<T, kEPT>), dim3((h->n2 + Lz.tile - 1) / Lz.tile, h->n1), dim3(Lz.nthr), Lz.lds,
+                     h->stream, S, grad, F3, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
+  stage_end(h, VDWXC_STAGE_DIV_Z);
+  stage_begin(h);
+  hipLaunchKernelGGL((k_div_y<T, kEPT>), dim3((h->n3 + Ly.tile - 1) / Ly.tile, h->n1), dim3(Ly.nthr), Ly.lds,
+                     h->stream, F3, F2, Prec<T>::tw(h, 1), h->geo, h->plan[1], Ly.tile, Ly.lstride);
+  stage_end(h, VDWXC_STAGE_DIV_Y);
+  stage_begin(h);
+  hipLaunchKernelGGL((k_div_x<T, kEPT>), dim3((h->n3 + Lx.tile - 1) / Lx.tile, h->n2), dim3(Lx.nthr), Lx.lds,
+                     h->stream, F2, v, Prec<T>::tw(h, 0), h->geo, h->plan[0], Lx.tile, Lx.lstride);
+  stage_end(h, VDWXC_STAGE_DIV_X);
 }
 
 // the five steps: theta + z FFT, y FFT, x FFT + contraction + inverse x, inverse y, inverse z +
@@ -574,15 +622,15 @@ vdwxc_status run_potential(vdwxc_ctx* h, const double* n, const double* grad, do
   const double* g = grad;
   if (!g) {
     // the gradient feeds q0, so it is taken in FP64 in both precisions
-    enqueue_spectral<double>(h, 0, n, nullptr, 1, 3, h->d_G);
+    enqueue_gradient<double>(h, n, h->d_G);
     g = h->d_G;
   }
   if (h->precision == VDWXC_FP64) {
     enqueue_main<double>(h, n, g, true, v, h->d_S, energy_dev);
-    enqueue_spectral<double>(h, 1, h->d_S, g, 3, 1, v);
+    enqueue_divergence<double>(h, h->d_S, g, v);
   } else {
     enqueue_main<float>(h, n, g, true, v, h->d_S, energy_dev);
-    enqueue_spectral<float>(h, 1, h->d_S, g, 3, 1, v);
+    enqueue_divergence<float>(h, h->d_S, g, v);
   }
   return finish_launch(h);
 }
@@ -703,7 +751,7 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   }
   bool ok = line_launch(kMaxThreadsZ, h->n3, h->n2, 16, h->zl64) && line_launch(kMaxThreadsZ, h->n3, h->n2, 8, h->zl32) &&
             line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64) && line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32) &&
-            xline_launch(3, h->n1, h->n1, 16, h->xs64) && xline_launch(3, h->n1, h->n1, 8, h->xs32);
+            xline_launch(3, h->n1, h->n1, 16, h->xs64);
   {
     // contraction pass: one thread per k-point up to kMaxThreadsX (the kernel strides beyond)
     Launch& L = precision == VDWXC_FP64 ? h->xl64 : h->xl32;
@@ -831,6 +879,26 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     release(h);
     return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
   }
+  {
+    int zt = 2;   // first z tile of the y and x divergence passes: min(16, n3 rounded up), >= 2
+    while (zt < std::min(VDWXC_DIV_ZT, h->n3)) zt *= 2;
+    const int yt = std::min(kLineTile, h->n2);
+    set_lds_limit(k_div_z<double, kEPT>, kMaxLds);
+    set_lds_limit(k_div_y<double, kEPT>, kMaxLds);
+    set_lds_limit(k_div_x<double, kEPT>, kMaxLds);
+    set_lds_limit(k_div_z<float, kEPT>, kMaxLds);
+    set_lds_limit(k_div_y<float, kEPT>, kMaxLds);
+    set_lds_limit(k_div_x<float, kEPT>, kMaxLds);
+    if (!pick_div<double>(k_div_z<double, kEPT>, 2, h->n3, yt, h->dz64) ||
+        !pick_div<double>(k_div_y<double, kEPT>, 1, h->n2, zt, h->dy64) ||
+        !pick_div<double>(k_div_x<double, kEPT>, 0, h->n1, zt, h->dx64) ||
+        !pick_div<float>(k_div_z<float, kEPT>, 2, h->n3, yt, h->dz32) ||
+        !pick_div<float>(k_div_y<float, kEPT>, 1, h->n2, zt, h->dy32) ||
+        !pick_div<float>(k_div_x<float, kEPT>, 0, h->n1, zt, h->dx32)) {
+      release(h);
+      return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
+    }
+  }
 
   // dynamic LDS above the default limit
   set_lds_limit(k_theta_zfwd<double, kEPT, false>, h->lds_theta64);
@@ -839,12 +907,8 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_theta_zfwd<float, kEPT, true>, h->lds_theta32);
   set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA>, h->lds_asm64);
   set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA>, h->lds_asm32);
-  set_lds_limit(k_real_zfwd<double, kEPT, 0>, h->zl64.lds);
-  set_lds_limit(k_real_zfwd<double, kEPT, 1>, h->zl64.lds);
-  set_lds_limit(k_real_zfwd<float, kEPT, 1>, h->zl32.lds);
-  set_lds_limit(k_real_zinv<double, kEPT, false>, h->zl64.lds);
-  set_lds_limit(k_real_zinv<double, kEPT, true>, h->zl64.lds);
-  set_lds_limit(k_real_zinv<float, kEPT, true>, h->zl32.lds);
+  set_lds_limit(k_real_zfwd<double, kEPT>, h->zl64.lds);
+  set_lds_limit(k_real_zinv<double, kEPT>, h->zl64.lds);
   set_lds_limit(k_ypass<double, kEPT, -1>, h->yl64.lds);
   set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
@@ -852,9 +916,13 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_xcontract<double, kEPTC, kXPad, 1>, h->xl64.lds);
   set_lds_limit(k_xcontract<float, kEPTC, kXPad, 1>, h->xl32.lds);
   set_lds_limit(k_xcontract<float, kEPTC, kXPad, 4>, h->xl32.lds);
-  set_lds_limit(k_xspectral<double, kEPTX, 1, 3>, h->xs64.lds);
-  set_lds_limit(k_xspectral<double, kEPTX, 3, 1>, h->xs64.lds);
-  set_lds_limit(k_xspectral<float, kEPTX, 3, 1>, h->xs32.lds);
+  set_lds_limit(k_xgradient<double, kEPTX>, h->xs64.lds);
+  set_lds_limit(k_div_z<double, kEPT>, h->dz64.lds);
+  set_lds_limit(k_div_y<double, kEPT>, h->dy64.lds);
+  set_lds_limit(k_div_x<double, kEPT>, h->dx64.lds);
+  set_lds_limit(k_div_z<float, kEPT>, h->dz32.lds);
+  set_lds_limit(k_div_y<float, kEPT>, h->dy32.lds);
+  set_lds_limit(k_div_x<float, kEPT>, h->dx32.lds);
   (void)hipGetLastError();
   *out = h;
   return VDWXC_OK;
@@ -923,7 +991,7 @@ vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const do
 const char* vdwxc_stage_name(int stage) {
   static const char* names[VDWXC_NUM_STAGES] = {
       "theta_zfwd", "y_fwd", "x_contract", "y_inv", "z_assemble", "energy", "grad_z", "grad_y",
-      "grad_x", "grad_yi", "grad_zi", "div_z", "div_y", "div_x", "div_yi", "div_zi"};
+      "grad_x", "grad_yi", "grad_zi", "div_z", "div_y", "div_x"};
   return (stage >= 0 && stage < VDWXC_NUM_STAGES) ? names[stage] : "?";
 }
 
