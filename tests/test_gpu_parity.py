@@ -121,6 +121,23 @@ def test_partials_ragged_grids(dev, precision, grid, L, seed):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("grid,L,seed", [CASES[i] for i in (1, 2, 5, 6, 7, 8)])
+def test_potential_ragged_grids(dev, precision, grid, L, seed):
+    """Potential with an analytic gradient: the divergence passes on ragged tiles, odd and even
+    axes, and axes of length 1 and 2 (no Nyquist mode / nothing but the Nyquist mode)."""
+    say(f"[potential ragged] grid={grid} L={L} seed={seed} precision={precision}")
+    n, g, _ = ragged_case(grid, L, seed, floor=1e-4)
+    cell = inputs.cubic_cell(L)
+    E_ref, v_ref, _, _ = vdwdf.potential(n.numpy(), cell, KT, grad=g.numpy())
+    f = functional(grid, cell, precision)
+    E, v = f.potential(n.to(dev), g.to(dev))
+    tol = TOL[precision]
+    say(f"    E rel error {abs(E - E_ref) / abs(E_ref):.3e}")
+    assert abs(E - E_ref) <= tol["e"] * abs(E_ref), (E, E_ref)
+    close_fields(v.cpu(), v_ref, tol["f"], "v", n, tol["wl1"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("m", [7, 12, 4])
 def test_smaller_q_meshes(dev, precision, m):
     """q-meshes shorter than 20 points (4 is the smallest the library takes), odd and even: the
