@@ -65,7 +65,6 @@ def stage_bytes(stage: str, grid, precision: str, m: int = M) -> float:
         "x_contract": 2 * m * Nk * c,
         "y_inv": 2 * m * Nk * c,
         "z_assemble": m * Nk * c + st * N + 16 * N,   # F(kz), state in; v, dE/dsigma out
-        "energy": 8 * n2 * (n3 // 2 + 1),
         "div_z": 32 * N + 3 * r * N,                  # S + grad in; A, B1, B2 out
         "div_y": 5 * r * N,                            # A, B1, B2 in; A', B1' out
         "div_x": 2 * r * N + 16 * N,                   # A', B1' and v in; v out

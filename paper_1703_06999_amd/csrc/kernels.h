@@ -897,6 +897,37 @@ struct PairPrefetch {
   }
 };
 
+// ---- energy: fixed-order sum of the per-column partials (one block) ----------------------------
+// Eight independent loads in flight per thread, then a fixed reduction tree: the same inputs give
+// the same bits.  flag[0] is raised by the theta pass on a NaN input; it is moved to flag[1] (the
+// evaluation's result, read by the host) and cleared here, so the next evaluation starts from
+// zero.  `red` holds one double per wave; the block is synchronised on return.
+__device__ __forceinline__ void energy_reduce_block(const double* __restrict__ partials, int nparts, double scale,
+                                                    int* __restrict__ flag, double* __restrict__ out, double* red,
+                                                    int tid, int nthr) {
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i0 = tid; i0 < nparts; i0 += 8 * nthr) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * nthr;
+      if (i < nparts) acc[u] += partials[i];
+    }
+  }
+  double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < (nthr + 63) / 64; ++w) tot += red[w];
+    const int bad = flag[0];
+    out[0] = bad != 0 ? __builtin_nan("") : tot * scale;
+    flag[1] = bad;
+    flag[0] = 0;
+  }
+  __syncthreads();
+}
+
 // ---- pass 5: inverse z FFT + assembly of dE/dn, dE/dsigma (eqs. dedn, dedsigma) -------------
 // dE/dn = sum_a F_a [p_a + n p_a' dq0/dn],  dE/dsigma = sum_a F_a n p_a' dq0/dsigma, with F_a(r)
 // from the inverse transforms (1/N applied here).  The per-point spline state (b, t, n dq0/dn,
@@ -908,12 +939,18 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __restrict__ state,
                 double* __restrict__ dedn, double* __restrict__ dedsig,
                 const double* __restrict__ qmesh, const double* __restrict__ mm,
-                const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
+                const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride,
+                const double* __restrict__ partials, int nparts, double escale, int* __restrict__ flag,
+                double* __restrict__ energy) {
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
   const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
   const int tid = threadIdx.x, nthr = blockDim.x;
+  // the energy of the evaluation (the contraction pass left its partials), in the first block,
+  // with the line area of LDS as scratch before anything else uses it
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    energy_reduce_block(partials, nparts, escale, flag, energy, reinterpret_cast<double*>(smem), tid, nthr);
   int tile, x;
   zpass_block(tile, x);
   const int y0 = tile * ty;
@@ -1313,30 +1350,6 @@ k_div_x(const T* __restrict__ in, double* __restrict__ v, const typename Cx<T>::
           v[(size_t(x) * n2 + y) * n3 + z0 + zl] = old - double(div);
         }
       });
-}
-
-// ---- energy: fixed-order sum of the per-column partials --------------------------------------
-
-// flag[0] is raised by the theta pass on a NaN input; it is moved to flag[1] (the evaluation's
-// result, read by the host) and cleared here, so the next evaluation starts from zero.
-__global__ void __launch_bounds__(512)
-k_energy_reduce(const double* __restrict__ partials, int nparts, double scale, int* __restrict__ flag,
-                double* __restrict__ out) {
-  __shared__ double red[16];
-  const int tid = threadIdx.x;
-  double s = 0.0;
-  for (int i = tid; i < nparts; i += blockDim.x) s += partials[i];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = s;
-  __syncthreads();
-  if (tid == 0) {
-    double tot = 0.0;
-    for (int w = 0; w < (int(blockDim.x) + 63) / 64; ++w) tot += red[w];
-    const int bad = flag[0];
-    out[0] = bad != 0 ? __builtin_nan("") : tot * scale;
-    flag[1] = bad;
-    flag[0] = 0;
-  }
 }
 
 }  // namespace vdwxc

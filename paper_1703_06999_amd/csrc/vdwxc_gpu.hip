@@ -586,14 +586,11 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   stage_begin(h);
   const Launch& La = Prec<T>::za(h);
   const dim3 agrid((h->n2 + La.tile - 1) / La.tile, h->n1);
-  hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state, dedn,
-                     dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile, La.lstride);
-  stage_end(h, VDWXC_STAGE_Z_ASSEMBLE);
   const double N = double(h->n1) * h->n2 * h->n3;
-  stage_begin(h);
-  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(512), 0, h->stream, h->d_partials, h->n2 * h->h3,
-                     h->omega / (2.0 * N * N), h->d_flag, energy);
-  stage_end(h, VDWXC_STAGE_ENERGY);
+  hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state, dedn,
+                     dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile, La.lstride,
+                     h->d_partials, h->n2 * h->h3, h->omega / (2.0 * N * N), h->d_flag, energy);
+  stage_end(h, VDWXC_STAGE_Z_ASSEMBLE);
 }
 
 vdwxc_status check_handle(vdwxc_ctx* h) {
@@ -857,7 +854,7 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_partials), size_t(h->n2) * h->h3 * sizeof(double))) != hipSuccess)
     return bail(e, "energy partials");
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_energy), sizeof(double))) != hipSuccess) return bail(e, "energy");
-  // [0]: raised by the theta pass, [1]: the last evaluation's result (see k_energy_reduce)
+  // [0]: raised by the theta pass, [1]: the last evaluation's result (see energy_reduce_block)
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_flag), 2 * sizeof(int))) != hipSuccess) return bail(e, "flag");
   if ((e = hipMemsetAsync(h->d_flag, 0, 2 * sizeof(int), h->stream)) != hipSuccess ||
       (e = hipStreamSynchronize(h->stream)) != hipSuccess)
@@ -990,7 +987,7 @@ vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const do
 
 const char* vdwxc_stage_name(int stage) {
   static const char* names[VDWXC_NUM_STAGES] = {
-      "theta_zfwd", "y_fwd", "x_contract", "y_inv", "z_assemble", "energy", "grad_z", "grad_y",
+      "theta_zfwd", "y_fwd", "x_contract", "y_inv", "z_assemble", "grad_z", "grad_y",
       "grad_x", "grad_yi", "grad_zi", "div_z", "div_y", "div_x"};
   return (stage >= 0 && stage < VDWXC_NUM_STAGES) ? names[stage] : "?";
 }
