@@ -52,6 +52,7 @@ __host__ __device__ constexpr int lds_span(int n) {
 struct AxisPlan {
   int n;
   int nst;
+  int linear;   // every stage meets the conditions of the LIN addressing (padded layouts)
   int radix[kMaxStages];
   unsigned mnb[kMaxStages], mp[kMaxStages];
 };
@@ -228,14 +229,19 @@ template <int DIR, typename T2> struct SmallDft<7, DIR, T2> : OddDft<7, DIR, T2>
 
 // ---- one Stockham stage on LDS lines ---------------------------------------------------------
 
-template <int R, int MAXB, int DIR, int PS, typename T2>
+// LIN (padded layout, plan.linear): with blocks of B = 2^PS slots, lidx(a + b) = lidx(a) + lidx(b)
+// whenever a or b is a multiple of B.  In a linear plan every stage has B | n/R, B | pR and p | B or
+// B | p, so a butterfly's reads at i + r n/R sit at the stage-uniform offsets lidx(r n/R) from
+// lidx(i), and its writes at dst + r p at lidx(r p) from lidx(dst): one address per butterfly
+// instead of index arithmetic per element.
+template <int R, int MAXB, int DIR, int PS, bool LIN, typename T2>
 __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstride, int p, unsigned mnb, unsigned mp,
                                           const T2* __restrict__ tw, int tid, int nthr) {
   const int nb = n / R;
   const int total = nb * nlines;
   const int twstep = n / (p * R);
   T2 v[MAXB][R];
-  int dst[MAXB], lbase[MAXB];
+  int dst[MAXB], wbase[MAXB];
 #pragma unroll
   for (int c = 0; c < MAXB; ++c) {
     const int b = tid + c * nthr;
@@ -245,27 +251,43 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
       const int i = b - l * nb;
       const int k = i - fast_div(i, mp) * p;
       const T2* src = buf + l * lstride;
+      if constexpr (LIN) {
+        const T2* s0 = src + lidx<PS>(i);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[c][r] = src[lidx<PS>(i + r * nb)];
+        for (int r = 0; r < R; ++r) v[c][r] = s0[lidx<PS>(r * nb)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[c][r] = src[lidx<PS>(i + r * nb)];
+      }
       if (p > 1) {
+        // twiddle r is exp(-+2 pi i r k / (p R)) = tw[r k twstep]: a running index, no multiplies
+        const int kt = k * twstep;
+        int to = 0;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          T2 w = tw[r * k * twstep];
+          to += kt;
+          T2 w = tw[to];
           if (DIR > 0) w.y = -w.y;
           v[c][r] = cmul(v[c][r], w);
         }
       }
       SmallDft<R, DIR, T2>::run(v[c]);
       dst[c] = (i - k) * R + k;
-      lbase[c] = l * lstride;
+      wbase[c] = l * lstride + (LIN ? lidx<PS>(dst[c]) : 0);
     }
   }
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < MAXB; ++c) {
     if (dst[c] >= 0) {
+      T2* d = buf + wbase[c];
+      if constexpr (LIN) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lbase[c] + lidx<PS>(dst[c] + r * p)] = v[c][r];
+        for (int r = 0; r < R; ++r) d[lidx<PS>(r * p)] = v[c][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[lidx<PS>(dst[c] + r * p)] = v[c][r];
+      }
     }
   }
   __syncthreads();
@@ -275,13 +297,32 @@ __device__ __forceinline__ void fft_stage(T2* buf, int n, int nlines, int lstrid
 // must have synchronised after filling the lines; the lines are complete on return.  The plan
 // lists its radices grouped (all 16s, then 8s, 4, 2, 3s, 5s, 7s), so each radix runs in its own loop
 // and the register allocation of one stage kind does not inflate the others.
-template <int R, int EPT, int DIR, int PS, typename T2>
+template <int R, int EPT, int DIR, int PS, bool LIN, typename T2>
 __device__ __forceinline__ void run_stages(T2* buf, const AxisPlan& plan, int n, int count, int& s0, int& p,
                                            int nlines, int lstride, const T2* __restrict__ tw, int tid, int nthr) {
   for (int s = 0; s < count; ++s, ++s0) {
-    fft_stage<R, (EPT + R - 1) / R, DIR, PS>(buf, n, nlines, lstride, p, plan.mnb[s0], plan.mp[s0], tw, tid, nthr);
+    fft_stage<R, (EPT + R - 1) / R, DIR, PS, LIN>(buf, n, nlines, lstride, p, plan.mnb[s0], plan.mp[s0], tw, tid,
+                                                  nthr);
     p *= R;
   }
+}
+
+template <int EPT, int DIR, int PS, bool LIN, typename T2>
+__device__ __forceinline__ void lds_fft_stages(T2* buf, const AxisPlan& plan, int n, int nlines, int lstride,
+                                               const T2* __restrict__ tw, int tid, int nthr) {
+  int cnt[7] = {0, 0, 0, 0, 0, 0, 0};   // radix 16, 8, 4, 2, 3, 5, 7
+  for (int s = 0; s < plan.nst; ++s) {
+    const int R = plan.radix[s];
+    cnt[R == 16 ? 0 : R == 8 ? 1 : R == 4 ? 2 : R == 2 ? 3 : R == 3 ? 4 : R == 5 ? 5 : 6] += 1;
+  }
+  int p = 1, s0 = 0;
+  run_stages<16, EPT, DIR, PS, LIN>(buf, plan, n, cnt[0], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<8, EPT, DIR, PS, LIN>(buf, plan, n, cnt[1], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<4, EPT, DIR, PS, LIN>(buf, plan, n, cnt[2], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<2, EPT, DIR, PS, LIN>(buf, plan, n, cnt[3], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<3, EPT, DIR, PS, LIN>(buf, plan, n, cnt[4], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<5, EPT, DIR, PS, LIN>(buf, plan, n, cnt[5], s0, p, nlines, lstride, tw, tid, nthr);
+  run_stages<7, EPT, DIR, PS, LIN>(buf, plan, n, cnt[6], s0, p, nlines, lstride, tw, tid, nthr);
 }
 
 template <int EPT, int DIR, int PS = kLdsPadShift, typename T2>
@@ -291,19 +332,10 @@ __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
   // keep the per-stage constants of this call from being hoisted into registers that stay live
   // across a caller's loop around the transform
   asm volatile("" : "+s"(n));
-  int cnt[7] = {0, 0, 0, 0, 0, 0, 0};   // radix 16, 8, 4, 2, 3, 5, 7
-  for (int s = 0; s < plan.nst; ++s) {
-    const int R = plan.radix[s];
-    cnt[R == 16 ? 6 : R == 8 ? 0 : R == 4 ? 1 : R == 2 ? 2 : R == 3 ? 3 : R == 5 ? 4 : 5] += 1;
-  }
-  int p = 1, s0 = 0;
-  run_stages<16, EPT, DIR, PS>(buf, plan, n, cnt[6], s0, p, nlines, lstride, tw, tid, nthr);
-  run_stages<8, EPT, DIR, PS>(buf, plan, n, cnt[0], s0, p, nlines, lstride, tw, tid, nthr);
-  run_stages<4, EPT, DIR, PS>(buf, plan, n, cnt[1], s0, p, nlines, lstride, tw, tid, nthr);
-  run_stages<2, EPT, DIR, PS>(buf, plan, n, cnt[2], s0, p, nlines, lstride, tw, tid, nthr);
-  run_stages<3, EPT, DIR, PS>(buf, plan, n, cnt[3], s0, p, nlines, lstride, tw, tid, nthr);
-  run_stages<5, EPT, DIR, PS>(buf, plan, n, cnt[4], s0, p, nlines, lstride, tw, tid, nthr);
-  run_stages<7, EPT, DIR, PS>(buf, plan, n, cnt[5], s0, p, nlines, lstride, tw, tid, nthr);
+  if (PS < kNoPad && plan.linear)
+    lds_fft_stages<EPT, DIR, PS, true>(buf, plan, n, nlines, lstride, tw, tid, nthr);
+  else
+    lds_fft_stages<EPT, DIR, PS, false>(buf, plan, n, nlines, lstride, tw, tid, nthr);
 }
 
 }  // namespace vdwxc

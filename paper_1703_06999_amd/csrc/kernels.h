@@ -934,14 +934,14 @@ __device__ __forceinline__ void energy_reduce_block(const double* __restrict__ p
 // n dq0/dsigma), computed in FP64 by the forward theta pass and stored in the path's precision,
 // is read once into LDS; the two sums sit in FP64 registers.
 
-template <typename T, int PPT, int EPT>
+template <typename T, int PPT, int EPT, int PB>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? VDWXC_WPE_ASM : 1)))
 k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __restrict__ state,
                 double* __restrict__ dedn, double* __restrict__ dedsig,
                 const double* __restrict__ qmesh, const double* __restrict__ mm,
                 const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride,
                 const double* __restrict__ partials, int nparts, double escale, int* __restrict__ flag,
-                double* __restrict__ energy) {
+                double* __restrict__ energy, int sets) {
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
@@ -957,8 +957,8 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __res
   const int n3 = g.n3, M = g.M;
   const size_t N = size_t(g.n1) * g.n2 * n3;
   const int npts = ty * n3;
-  T2* line = reinterpret_cast<T2*>(smem);
-  size_t off = size_t(ty) * lstride * sizeof(T2);
+  T2* line = reinterpret_cast<T2*>(smem);   // `sets` (<= PB) line sets of ty lines, one per pair of a batch
+  size_t off = size_t(sets) * ty * lstride * sizeof(T2);
   T* st_t = reinterpret_cast<T*>(smem + off);
   off += size_t(npts) * sizeof(T);
   T* st_an = reinterpret_cast<T*>(smem + off);
@@ -1006,21 +1006,36 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __res
       Fb[c] = Fb1[c] = T(0);
     }
   }
+  // field pairs in batches of `sets`: one transform of sets * ty lines per batch (fewer, fuller FFT
+  // stages), the next batch's half spectra in flight meanwhile
   const int npairs = (M + 1) >> 1;
-  PairPrefetch<T2, EPT / 2 + 1> pf;
-  pf.issue(A, g, 0, M > 1 ? 1 : -1, x, y0, ty, tid, nthr);
+  PairPrefetch<T2, EPT / 2 + 1> pf[PB];
+#pragma unroll
+  for (int q = 0; q < PB; ++q)
+    if (q < sets && q < npairs) pf[q].issue(A, g, 2 * q, 2 * q + 1 < M ? 2 * q + 1 : -1, x, y0, ty, tid, nthr);
 #pragma unroll 1
-  for (int pr = 0; pr < npairs; ++pr) {
-    const int fa = 2 * pr, fb = 2 * pr + 1 < M ? 2 * pr + 1 : -1;
-    pf.store(g, ty, line, lstride, tid, nthr);
+  for (int pr0 = 0; pr0 < npairs; pr0 += sets) {
+    const int nb = min(sets, npairs - pr0);
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      if (q < nb) pf[q].store(g, ty, line + q * ty * lstride, lstride, tid, nthr);
     __syncthreads();
-    if (pr + 1 < npairs) pf.issue(A, g, fa + 2, fa + 3 < M ? fa + 3 : -1, x, y0, ty, tid, nthr);
-    lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int pn = pr0 + sets + q;
+      if (q < sets && pn < npairs) pf[q].issue(A, g, 2 * pn, 2 * pn + 1 < M ? 2 * pn + 1 : -1, x, y0, ty, tid, nthr);
+    }
+    lds_fft<PB * EPT, +1>(line, zp, nb * ty, lstride, twl, tid, nthr);
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      if (q >= nb) break;
+      const int fa = 2 * (pr0 + q), fb = fa + 1 < M ? fa + 1 : -1;
+      const T2* lq = line + q * ty * lstride;
 #pragma unroll
     for (int c = 0; c < PPT; ++c) {
       const int b = bb[c];
       if (b != 255) {
-        const T2 F = line[loff[c]];
+        const T2 F = lq[loff[c]];
         // m entries of fields fa, fa+1 at knots b and b+1 (adjacent in the transposed table)
         const T2 m0 = *reinterpret_cast<const T2*>(S.mmT + b * kMaxQ + fa);
         const T2 m1 = *reinterpret_cast<const T2*>(S.mmT + (b + 1) * kMaxQ + fa);
@@ -1032,6 +1047,7 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __res
         if (fa == b + 1) Fb1[c] = F.x;
         if (fb == b + 1) Fb1[c] = F.y;
       }
+    }
     }
     __syncthreads();
   }

@@ -29,6 +29,11 @@ namespace {
 #ifndef VDWXC_DIV_ZT
 #define VDWXC_DIV_ZT 16
 #endif
+// field pairs per inverse z transform in the assembly: two in FP64 (192^3: -20 % in that pass);
+// one in FP32, where the second prefetch set spills under the 128-register cap and costs
+// occupancy without it
+template <typename T>
+constexpr int asm_pb() { return sizeof(T) == 8 ? 2 : 1; }
 constexpr int kEPTA = 4;         // grid points (and FFT elements) per thread in the z assembly
 constexpr int kEPT = 8;          // FFT elements per thread in the z and y passes
 #ifndef VDWXC_EPTX
@@ -58,6 +63,7 @@ thread_local std::string g_init_error;
 struct Launch {
   int tile = 1, nthr = 64, lstride = 1;
   size_t lds = 0;
+  int sets = 1;   // assembly: line sets (field pairs per transform)
 };
 
 }  // namespace
@@ -149,10 +155,14 @@ bool factor_axis(int n, AxisPlan& p) {
   }
   if (m != 1) return false;
   int prod = 1;
+  const int B = 1 << kLdsPadShift;
+  p.linear = 1;
   for (int s = 0; s < p.nst; ++s) {
-    p.mnb[s] = div_magic(unsigned(n / p.radix[s]));
+    const int R = p.radix[s], nb = n / R;
+    p.mnb[s] = div_magic(unsigned(nb));
     p.mp[s] = div_magic(unsigned(prod));
-    prod *= p.radix[s];
+    if (nb % B != 0 || (prod * R) % B != 0 || (prod % B != 0 && B % prod != 0)) p.linear = 0;
+    prod *= R;
   }
   return true;
 }
@@ -331,7 +341,7 @@ bool pick_occupancy(K* kernel, const Cand* c, int nc, Launch& out, size_t& lds_o
 // z passes with per-point state: `values` values of type T per point sit next to the lines
 // (zstate_lds).  Tiles halve from min(kLineTile, other).
 template <typename T, typename K>
-bool pick_ztile(K* kernel, int n3, int other, int values, int ept, Launch& out, size_t& lds_out) {
+bool pick_ztile(K* kernel, int n3, int other, int values, int ept, Launch& out, size_t& lds_out, int line_sets = 1) {
   Cand c[8];
   int nc = 0;
   for (int tile = std::min(kLineTile, std::max(1, other)); tile >= 1 && nc < 8; tile /= 2) {
@@ -339,8 +349,9 @@ bool pick_ztile(K* kernel, int n3, int other, int values, int ept, Launch& out, 
     if (!zline_config(tile, n3, 2 * sizeof(T), ept, L)) continue;
     // one-wave blocks only where nothing larger fits: their per-block set-up is not repaid
     if (nc > 0 && L.nthr < 128) break;
-    const size_t lds = zstate_lds<T>(L, n3, values);
+    const size_t lds = zstate_lds<T>(L, n3, values) + size_t(line_sets - 1) * tile * L.lstride * 2 * sizeof(T);
     if (lds > kMaxLds) continue;
+    L.sets = line_sets;
     c[nc++] = Cand{L, lds};
   }
   return pick_occupancy(kernel, c, nc, out, lds_out);
@@ -587,9 +598,9 @@ void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_fro
   const Launch& La = Prec<T>::za(h);
   const dim3 agrid((h->n2 + La.tile - 1) / La.tile, h->n1);
   const double N = double(h->n1) * h->n2 * h->n3;
-  hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state, dedn,
+  hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, asm_pb<T>()>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state, dedn,
                      dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile, La.lstride,
-                     h->d_partials, h->n2 * h->h3, h->omega / (2.0 * N * N), h->d_flag, energy);
+                     h->d_partials, h->n2 * h->h3, h->omega / (2.0 * N * N), h->d_flag, energy, La.sets);
   stage_end(h, VDWXC_STAGE_Z_ASSEMBLE);
 }
 
@@ -867,12 +878,18 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   // z tiles by occupancy (the plain-field z passes share the theta tile)
   set_lds_limit(k_theta_zfwd<double, kEPT, true>, kMaxLds);
   set_lds_limit(k_theta_zfwd<float, kEPT, true>, kMaxLds);
-  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA>, kMaxLds);
-  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA>, kMaxLds);
+  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA, asm_pb<double>()>, kMaxLds);
+  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA, asm_pb<float>()>, kMaxLds);
   if (!pick_ztile<double>(k_theta_zfwd<double, kEPT, true>, h->n3, h->n2, 2, kEPT, h->zl64, h->lds_theta64) ||
       !pick_ztile<float>(k_theta_zfwd<float, kEPT, true>, h->n3, h->n2, 2, kEPT, h->zl32, h->lds_theta32) ||
-      !pick_ztile<double>(k_zinv_assemble<double, kEPTA, kEPTA>, h->n3, h->n2, 3, kEPTA, h->za64, h->lds_asm64) ||
-      !pick_ztile<float>(k_zinv_assemble<float, kEPTA, kEPTA>, h->n3, h->n2, 3, kEPTA, h->za32, h->lds_asm32)) {
+      !(pick_ztile<double>(k_zinv_assemble<double, kEPTA, kEPTA, asm_pb<double>()>, h->n3, h->n2, 3, kEPTA, h->za64,
+                           h->lds_asm64, asm_pb<double>()) ||
+        pick_ztile<double>(k_zinv_assemble<double, kEPTA, kEPTA, asm_pb<double>()>, h->n3, h->n2, 3, kEPTA, h->za64,
+                           h->lds_asm64, 1)) ||
+      !(pick_ztile<float>(k_zinv_assemble<float, kEPTA, kEPTA, asm_pb<float>()>, h->n3, h->n2, 3, kEPTA, h->za32,
+                          h->lds_asm32, asm_pb<float>()) ||
+        pick_ztile<float>(k_zinv_assemble<float, kEPTA, kEPTA, asm_pb<float>()>, h->n3, h->n2, 3, kEPTA, h->za32,
+                          h->lds_asm32, 1))) {
     release(h);
     return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
   }
@@ -902,8 +919,8 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_theta_zfwd<double, kEPT, true>, h->lds_theta64);
   set_lds_limit(k_theta_zfwd<float, kEPT, false>, h->lds_theta32);
   set_lds_limit(k_theta_zfwd<float, kEPT, true>, h->lds_theta32);
-  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA>, h->lds_asm64);
-  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA>, h->lds_asm32);
+  set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA, asm_pb<double>()>, h->lds_asm64);
+  set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA, asm_pb<float>()>, h->lds_asm32);
   set_lds_limit(k_real_zfwd<double, kEPT>, h->zl64.lds);
   set_lds_limit(k_real_zinv<double, kEPT>, h->zl64.lds);
   set_lds_limit(k_ypass<double, kEPT, -1>, h->yl64.lds);
