@@ -681,36 +681,34 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     if (j > g.nk - 2) j = g.nk - 2;
     const T w = T(inside ? sc - j : 0.0);
     // Table entry (group g, node j) = T_j of pairs 2g and 2g+1, then their differences
-    // T_j+1 - T_j, so phi = T_j + w (T_j+1 - T_j) is one FMA.  Buffer loads: the lane's node
-    // offset in one VGPR, the group's offset in an SGPR, advanced through one running offset
-    // that is laundered after every step (otherwise all 105 group offsets are formed up front
-    // and stay live).  Each pair is read and interpolated once (phi is symmetric) and feeds
-    // F_a += phi theta_b and F_b += phi theta_a.  The loads run kXChunk at a time, the next
-    // chunk's issued before the current chunk's arithmetic.
-    const int joff = j * int(sizeof(Quad<T>));
-    const int gstride = g.nk * int(sizeof(Quad<T>));
-    const __amdgpu_buffer_rsrc_t trs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<Quad<T>*>(table4), short(0), gstride * (kNumPairs / 2), kBufferWord3);
-    int tcur = 0;
-#define VDWXC_TLOAD(dst)                                                                          \
-  do {                                                                                            \
-    asm volatile("" : "+s"(tcur));                                                                \
-    buffer_load_quad(trs, joff, tcur, (dst));                                                     \
-    tcur += gstride;                                                                              \
-  } while (0)
+    // T_j+1 - T_j, so phi = T_j + w (T_j+1 - T_j) is one FMA.  The entries are stored chunk-major,
+    // [g / kXChunk][j][g % kXChunk]: the kXChunk entries a lane reads for one chunk are adjacent,
+    // so a chunk's loads share cache lines.  Buffer loads: the lane's node offset in one VGPR
+    // (plus the entry's place in the chunk as an immediate), the chunk's offset in an SGPR,
+    // advanced through one running offset that is laundered after every chunk (otherwise all
+    // chunk offsets are formed up front and stay live).  Each pair is read and interpolated once
+    // (phi is symmetric) and feeds F_a += phi theta_b and F_b += phi theta_a.  The next chunk's
+    // loads are issued before the current chunk's arithmetic.
     constexpr int kGroups = kNumPairs / 2;
     constexpr int kChunks = (kGroups + kXChunk - 1) / kXChunk;
+    constexpr int kQ = int(sizeof(Quad<T>));
+    const int joff = j * (kXChunk * kQ);
+    const int cstride = g.nk * (kXChunk * kQ);
+    const __amdgpu_buffer_rsrc_t trs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<Quad<T>*>(table4), short(0), cstride * kChunks, kBufferWord3);
+    int tcur = 0;
+#define VDWXC_TLOAD_CHUNK(dst, cc)                                                                \
+  do {                                                                                            \
+    asm volatile("" : "+s"(tcur));                                                                \
+    _Pragma("unroll") for (int i = 0; i < kXChunk; ++i)                                           \
+      if ((cc) * kXChunk + i < kGroups) buffer_load_quad(trs, joff + i * kQ, tcur, (dst)[i]);     \
+    tcur += cstride;                                                                              \
+  } while (0)
     Quad<T> buf[2][kXChunk];
-#pragma unroll
-    for (int i = 0; i < kXChunk; ++i)
-      if (i < kGroups) VDWXC_TLOAD(buf[0][i]);
+    VDWXC_TLOAD_CHUNK(buf[0], 0);
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-      if (c + 1 < kChunks) {
-#pragma unroll
-        for (int i = 0; i < kXChunk; ++i)
-          if ((c + 1) * kXChunk + i < kGroups) VDWXC_TLOAD(buf[(c + 1) & 1][i]);
-      }
+      if (c + 1 < kChunks) VDWXC_TLOAD_CHUNK(buf[(c + 1) & 1], c + 1);
 #pragma unroll
       for (int i = 0; i < kXChunk; ++i) {
         const int grp = c * kXChunk + i;
@@ -744,7 +742,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
 #pragma unroll
         for (int a = 0; a < kMaxQ; ++a) asm volatile("" : "+v"(F[q][a].x), "+v"(F[q][a].y));
     }
-#undef VDWXC_TLOAD
+#undef VDWXC_TLOAD_CHUNK
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
       if (valid[q]) {

@@ -820,9 +820,11 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   if ((e = upload(&h->d_mm, mm.data(), mm.size())) != hipSuccess) return bail(e, "spline upload");
   {
     // per unordered pair p = (a <= b) and node j: T_j and T_j+1 - T_j (0 at the last node);
-    // pairs 2g and 2g+1 share entry [g][j] = (T_j(2g), T_j(2g+1), D_j(2g), D_j(2g+1)).  Pairs
-    // with a or b >= nq stay zero.
-    const size_t tn = size_t(kNumPairs / 2) * nk;
+    // pairs 2g and 2g+1 share entry (g, j) = (T_j(2g), T_j(2g+1), D_j(2g), D_j(2g+1)), stored
+    // chunk-major at [g / kXChunk][j][g % kXChunk] (the contraction reads a chunk's entries of
+    // one node together).  Pairs with a or b >= nq stay zero.
+    constexpr int kGroups = kNumPairs / 2, kChunks = (kGroups + kXChunk - 1) / kXChunk;
+    const size_t tn = size_t(kChunks) * kXChunk * nk;
     std::vector<Quad<double>> t64(tn, Quad<double>{0.0, 0.0, 0.0, 0.0});
     for (int a = 0; a < nq; ++a)
       for (int b = a; b < nq; ++b) {
@@ -830,7 +832,8 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
         for (int j = 0; j < nk; ++j) {
           const double tj = table[(size_t(j) * nq + a) * nq + b];
           const double dj = j + 1 < nk ? table[(size_t(j + 1) * nq + a) * nq + b] - tj : 0.0;
-          Quad<double>& q = t64[size_t(pr / 2) * nk + j];
+          const int grp = pr / 2;
+          Quad<double>& q = t64[(size_t(grp / kXChunk) * nk + j) * kXChunk + grp % kXChunk];
           if (pr % 2 == 0) {
             q.x = tj;
             q.z = dj;
