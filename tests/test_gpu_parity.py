@@ -137,6 +137,47 @@ def test_potential_ragged_grids(dev, precision, grid, L, seed):
     close_fields(v.cpu(), v_ref, tol["f"], "v", n, tol["wl1"])
 
 
+def smooth_periodic(grid, lengths):
+    """n = n0 (1 + 0.6 cos(2 pi x/Lx) cos(2 pi y/Ly) cos(2 pi z/Lz)) on a rectangular cell, with its
+    analytic gradient: a positive density whose spectrum has a few modes only."""
+    ax = [np.arange(k) * (L / k) for k, L in zip(grid, lengths)]
+    X, Y, Z = np.meshgrid(*ax, indexing="ij")
+    kx, ky, kz = (2 * np.pi / L for L in lengths)
+    cx, cy, cz = np.cos(kx * X), np.cos(ky * Y), np.cos(kz * Z)
+    sx, sy, sz = np.sin(kx * X), np.sin(ky * Y), np.sin(kz * Z)
+    n0 = 0.05
+    n = n0 * (1.0 + 0.6 * cx * cy * cz)
+    g = np.stack([-0.6 * n0 * kx * sx * cy * cz, -0.6 * n0 * ky * cx * sy * cz, -0.6 * n0 * kz * cx * cy * sz])
+    return torch.from_numpy(n), torch.from_numpy(g)
+
+
+@pytest.mark.parametrize("precision,grid", [
+    ("fp32", (1024, 2, 4)),   # the longest x axis in FP32: 20 lines of 1024 fill the 160 KiB of LDS
+    ("fp64", (512, 2, 4)),    # the longest x axis in FP64
+    ("fp32", (2, 2048, 2)),   # the longest y axis
+    ("fp64", (2, 2, 2048)),   # the longest z axis (the assembly falls back to one line set)
+    ("fp32", (4, 4, 2048)),
+])
+def test_maximum_axis_lengths(dev, precision, grid):
+    say(f"[maximum axes] grid={grid} {precision}")
+    lengths = [0.15 * k for k in grid]   # |G| at the corner stays below the table's k_max
+    cell = np.diag(lengths)
+    n, g = smooth_periodic(grid, lengths)
+    sigma = (g * g).sum(0)
+    tol = TOL[precision]
+    E_ref, dn_ref, ds_ref = vdwdf.energy_and_partials(n.numpy(), sigma.numpy(), cell, KT)
+    f = functional(grid, cell, precision)
+    E, dn, ds = f.calculate(n.to(dev), sigma.to(dev))
+    say(f"    E rel error {abs(E - E_ref) / abs(E_ref):.3e}")
+    assert abs(E - E_ref) <= tol["e"] * abs(E_ref), (E, E_ref)
+    close_fields(dn.cpu(), dn_ref, tol["f"], "dedn", n, tol["wl1"])
+    close_fields(ds.cpu(), ds_ref, tol["fs"], "dedsigma", n, tol["wl1s"])
+    E_ref, v_ref, _, _ = vdwdf.potential(n.numpy(), cell, KT, grad=g.numpy())
+    E, v = f.potential(n.to(dev), g.to(dev))
+    assert abs(E - E_ref) <= tol["e"] * abs(E_ref), (E, E_ref)
+    close_fields(v.cpu(), v_ref, tol["f"], "v", n, tol["wl1"])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("m", [7, 12, 4])
 def test_smaller_q_meshes(dev, precision, m):
