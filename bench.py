@@ -134,7 +134,11 @@ def main() -> int:
     kt = inputs.synthetic_kernel_table()
     w = inputs.workload(args.workload)
     print(f"[bench] workload {args.workload} grid {w.grid} precision {args.precision}", file=sys.stderr, flush=True)
-    n, g = w.density(device="cuda")
+    t_in = time.perf_counter()
+    n, g = w.density(device="cuda", progress=lambda done, total: print(
+        f"[bench] density: {done}/{total} blobs", file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    print(f"[bench] density ready in {time.perf_counter() - t_in:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     f = vdwxc.Functional(w.grid, w.cell, flavour="DF1", precision=args.precision, table=kt)
     v = torch.empty_like(n)

@@ -153,11 +153,12 @@ def gaussian_pair_density(grid, length_bohr: float, centres_bohr, width_bohr: fl
 
 
 def slater_blob_density(grid, length_bohr: float, centres_bohr: np.ndarray, zetas: np.ndarray,
-                        device: str = "cpu"):
+                        device: str = "cpu", progress=None):
     """n = sum_i (zeta_i^3/pi) exp(-2 zeta_i d_i) on a periodic cubic cell, d_i the minimum-image
     distance; each blob is cut off where exp(-2 zeta d) < 1e-20.  Returns torch float64 tensors
     (n [N1,N2,N3], grad [3,N1,N2,N3]) on ``device``.  Each blob is added on its own sub-box of
-    the grid, in blob order, so the bytes are reproducible for a given device."""
+    the grid, in blob order, so the bytes are reproducible for a given device.  ``progress``, if
+    given, is called as progress(done, total) after every 1000 blobs."""
     torch = _torch()
     n1, n2, n3 = (int(g) for g in grid)
     dims = (n1, n2, n3)
@@ -166,7 +167,10 @@ def slater_blob_density(grid, length_bohr: float, centres_bohr: np.ndarray, zeta
     dev = torch.device(device)
     n = torch.zeros(dims, dtype=torch.float64, device=dev)
     grad = torch.zeros((3,) + dims, dtype=torch.float64, device=dev)
-    for c, z in zip(np.asarray(centres_bohr, dtype=np.float64), np.asarray(zetas, dtype=np.float64)):
+    total = len(zetas)
+    for done, (c, z) in enumerate(zip(np.asarray(centres_bohr, dtype=np.float64), np.asarray(zetas, dtype=np.float64))):
+        if progress is not None and done and done % 1000 == 0:
+            progress(done, total)
         dcut = SLATER_CUTOFF_EXPONENT / (2.0 * z)
         idx, dist = [], []
         for ax in range(3):
@@ -276,8 +280,8 @@ class Workload:
     def npoints(self) -> int:
         return int(np.prod(self.grid))
 
-    def density(self, device: str = "cpu"):
-        """(n, grad) as torch float64 tensors on ``device``."""
+    def density(self, device: str = "cpu", progress=None):
+        """(n, grad) as torch float64 tensors on ``device`` (``progress``: see slater_blob_density)."""
         torch = _torch()
         L = float(self.cell[0, 0])
         if self.name.startswith("serving_"):
@@ -287,7 +291,7 @@ class Workload:
             cB = np.array([4.0 + 1.75, 4.0, 4.0]) * ANGSTROM
             n, g = gaussian_pair_density(self.grid, L, [cA, cB], 0.8 * ANGSTROM, 0.3, 1e-6)
             return (torch.from_numpy(n).to(device), torch.from_numpy(g).to(device))
-        return slater_blob_density(self.grid, L, self.centres, self.zetas, device=device)
+        return slater_blob_density(self.grid, L, self.centres, self.zetas, device=device, progress=progress)
 
 
 def workload(name: str, grid_n: int | None = None, seed_offset: int = 0) -> Workload:
