@@ -121,8 +121,8 @@ def main() -> int:
                          "kernel of known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not supported "
-              "(the slab/all-to-all design is described, not built)", file=sys.stderr)
+        print("bench.py: the library runs on one GPU and has no multi-GPU path (the slab decomposition "
+              "with all-to-all exchanges is a design only)", file=sys.stderr)
         return 2
 
     import numpy as np

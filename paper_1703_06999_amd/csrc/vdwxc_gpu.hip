@@ -23,9 +23,6 @@ using namespace vdwxc;
 
 namespace {
 
-#ifndef VDWXC_RADIX16
-#define VDWXC_RADIX16 1
-#endif
 #ifndef VDWXC_DIV_ZT
 #define VDWXC_DIV_ZT 16
 #endif
@@ -138,11 +135,7 @@ bool factor_axis(int n, AxisPlan& p) {
   // an 8 where it saves a stage (2^7 = 16 * 8 rather than 8 * 8 * 2)
   int e = 0;
   while (m % 2 == 0) { m /= 2; ++e; }
-#if VDWXC_RADIX16
   const int n16 = e % 3 == 1 && e >= 4 ? 1 : e % 3 == 2 && e >= 8 ? 2 : 0;
-#else
-  const int n16 = 0;
-#endif
   for (int i = 0; i < n16; ++i) { p.radix[p.nst++] = 16; e -= 4; }
   while (e >= 3) { p.radix[p.nst++] = 8; e -= 3; }
   if (e > 0) p.radix[p.nst++] = 1 << e;
