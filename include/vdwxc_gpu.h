@@ -127,15 +127,13 @@ typedef enum {
   VDWXC_STAGE_X_CONTRACT = 2,   /* forward x FFT, k-space contraction + energy, inverse x FFT (steps 2-4) */
   VDWXC_STAGE_Y_INV = 3,        /* inverse y FFT of the F fields */
   VDWXC_STAGE_Z_ASSEMBLE = 4,   /* inverse z FFT and dE/dn, dE/dsigma (steps 4-5); fixed-order energy sum */
-  VDWXC_STAGE_GRAD_Z = 5,       /* spectral gradient of n: z, y, x, y, z passes */
-  VDWXC_STAGE_GRAD_Y = 6,
+  VDWXC_STAGE_GRAD_Z = 5,       /* spectral gradient of n (no gradient given), one axis per pass: */
+  VDWXC_STAGE_GRAD_Y = 6,       /* z, y, x */
   VDWXC_STAGE_GRAD_X = 7,
-  VDWXC_STAGE_GRAD_YI = 8,
-  VDWXC_STAGE_GRAD_ZI = 9,
-  VDWXC_STAGE_DIV_Z = 10,       /* spectral divergence of 2 dE/dsigma grad n, one axis per pass: */
-  VDWXC_STAGE_DIV_Y = 11,       /* z, y, x (the x pass subtracts it from the potential) */
-  VDWXC_STAGE_DIV_X = 12,
-  VDWXC_NUM_STAGES = 13
+  VDWXC_STAGE_DIV_Z = 8,        /* spectral divergence of 2 dE/dsigma grad n, one axis per pass: */
+  VDWXC_STAGE_DIV_Y = 9,        /* z, y, x (the x pass subtracts it from the potential) */
+  VDWXC_STAGE_DIV_X = 10,
+  VDWXC_NUM_STAGES = 11
 } vdwxc_stage;
 
 /* Per-stage timing with HIP events recorded on the handle's stream around every kernel launch

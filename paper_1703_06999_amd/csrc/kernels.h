@@ -135,20 +135,11 @@ __device__ __forceinline__ void split_pair(T2 zk, T2 zn, T2& xa, T2& xb) {
 #ifndef VDWXC_WPE_THETA
 #define VDWXC_WPE_THETA 4
 #endif
-#ifndef VDWXC_WPE_REALZ
-#define VDWXC_WPE_REALZ 1
-#endif
 #ifndef VDWXC_WPE_Y
 #define VDWXC_WPE_Y 1
 #endif
-#ifndef VDWXC_WPE_XS
-#define VDWXC_WPE_XS 1
-#endif
 #ifndef VDWXC_WPE_ASM
 #define VDWXC_WPE_ASM 4   // FP32 assembly: <= 128 VGPRs, two 512-thread blocks per CU
-#endif
-#ifndef VDWXC_WPE_REALZI
-#define VDWXC_WPE_REALZI 1
 #endif
 
 // ---- strided gathers with several loads in flight -------------------------------------------
@@ -420,64 +411,6 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
         T2* dst = Aa + size_t(kz) * kzstride + yl;
         dst[0] = xa;
         if (fb < M) dst[fstride] = xb;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ---- pass 1 for plain real fields (spectral gradient input) ---------------------------------
-// nf FP64 fields read from src[f*N + idx], transformed in pairs (one complex line per two fields).
-
-template <typename T, int EPT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_REALZ)))
-k_real_zfwd(const double* __restrict__ src, int nf, typename Cx<T>::type* __restrict__ A,
-            const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
-  using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
-  const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
-  T2* line = reinterpret_cast<T2*>(smem);
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  int tile, x;
-  zpass_block(tile, x);
-  const int y0 = tile * ty;
-  const int n3 = g.n3;
-  const size_t N = size_t(g.n1) * g.n2 * n3;
-  const int npts = ty * n3;
-#pragma unroll 1
-  for (int fa = 0; fa < nf; fa += 2) {
-    const int fb = fa + 1;
-    struct Raw {
-      double a, b;
-    };
-    gather_strided_dm<4>(
-        tid, nthr, npts, n3,
-        [&](int, int yl, int z) {
-          const int y = y0 + yl;
-          Raw r{0.0, 0.0};
-          if (y < g.n2) {
-            const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-            r.a = src[size_t(fa) * N + idx];
-            if (fb < nf) r.b = src[size_t(fb) * N + idx];
-          }
-          return r;
-        },
-        [&](int, int yl, int z, const Raw& r) { line[yl * lstride + lidx<>(z)] = T2{T(r.a), T(r.b)}; });
-    __syncthreads();
-    lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
-    const int nout = ty * g.h3;
-    DivModStep ot(tid, nthr, ty);
-#pragma unroll 1
-    for (int e = tid; e < nout; e += nthr, ot.next()) {
-      const int yl = ot.r, kz = ot.q, y = y0 + yl;
-      if (y < g.n2) {
-        const T2 zk = line[yl * lstride + lidx<>(kz)];
-        const T2 zn = line[yl * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
-        T2 xa, xb;
-        split_pair(zk, zn, xa, xb);
-        A[a_index(g, fa, kz, x, y)] = xa;
-        if (fb < nf) A[a_index(g, fb, kz, x, y)] = xb;
       }
     }
     __syncthreads();
@@ -778,53 +711,6 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
   }
 }
 
-// ---- pass 3 for the spectral gradient (1 -> 3 fields) ----------------------------------------
-// D_c f = IFFT(i G_c FFT f) with every frequency touching a Nyquist index set to zero.
-
-template <typename T, int EPT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_XS)))
-k_xgradient(typename Cx<T>::type* __restrict__ B, const typename Cx<T>::type* __restrict__ tw,
-            Geometry g, AxisPlan xp) {
-  constexpr int NIN = 1, NOUT = 3;
-  using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n1);
-  const T2* twl = stage_twiddles(smem_raw, tw, g.n1, threadIdx.x, blockDim.x);
-  T2* line = reinterpret_cast<T2*>(smem);
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int kz = blockIdx.x, ky = blockIdx.y, n1 = g.n1;
-  const int ls = lds_span<>(n1);
-  T2* cb = B + b_index(g, 0, ky, kz, 0);
-  const size_t fstride = size_t(g.n2) * g.h3 * n1;
-  gather_strided_dm<8>(
-      tid, nthr, NIN * n1, n1, [&](int, int f, int x) { return cb[size_t(f) * fstride + x]; },
-      [&](int, int f, int x, T2 v) { line[f * ls + lidx<>(x)] = v; });
-  __syncthreads();
-  const int G = (nthr * EPT) / n1;
-  for (int l0 = 0; l0 < NIN; l0 += G) lds_fft<EPT, -1>(line + l0 * ls, xp, min(G, NIN - l0), ls, twl, tid, nthr);
-  const bool nyq_yz = is_nyquist(ky, g.n2) || is_nyquist(kz, g.n3);
-  const double fy = signed_freq(ky, g.n2), fz = signed_freq(kz, g.n3);
-  for (int kx = tid; kx < n1; kx += nthr) {
-    const bool zero = nyq_yz || is_nyquist(kx, n1);
-    const double fx = signed_freq(kx, n1);
-    double G[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) G[c] = fx * g.bvec[c] + fy * g.bvec[3 + c] + fz * g.bvec[6 + c];
-    const T2 in = line[lidx<>(kx)];
-#pragma unroll
-    for (int c = 0; c < NOUT; ++c) {   // i G_c X
-      const T gc = zero ? T(0) : T(G[c]);
-      line[c * ls + lidx<>(kx)] = T2{-gc * in.y, gc * in.x};
-    }
-  }
-  __syncthreads();
-  for (int l0 = 0; l0 < NOUT; l0 += G) lds_fft<EPT, +1>(line + l0 * ls, xp, min(G, NOUT - l0), ls, twl, tid, nthr);
-  {
-    DivModStep it(tid, nthr, n1);
-    for (int e = tid; e < NOUT * n1; e += nthr, it.next()) cb[size_t(it.q) * fstride + it.r] = line[it.q * ls + lidx<>(it.r)];
-  }
-}
-
 // Rebuild the full complex z-line Z = X_a + i X_b of a field pair from their half spectra (the
 // imaginary parts of the k = 0 and Nyquist terms are dropped, as a complex-to-real transform does).
 template <typename T2>
@@ -837,28 +723,6 @@ __device__ __forceinline__ void store_pair_values(T2 xa, T2 xb, int kz, int yl, 
   }
   line[yl * lstride + lidx<>(kz)] = T2{xa.x - xb.y, xa.y + xb.x};
   if (!edge) line[yl * lstride + lidx<>(n3 - kz)] = T2{xa.x + xb.y, xb.x - xa.y};
-}
-
-template <typename T2>
-__device__ __forceinline__ void load_pair_line(const T2* __restrict__ A, const Geometry& g, int fa, int fb,
-                                               int x, int y0, int ty, T2* line, int lstride, int tid, int nthr) {
-  using T = decltype(line[0].x);
-  const int n3 = g.n3, tot = ty * g.h3;
-  struct Pair {
-    T2 a, b;
-  };
-  gather_strided_dm<8>(
-      tid, nthr, tot, ty,
-      [&](int, int kz, int yl) {
-        const int y = y0 + yl;
-        Pair r{T2{T(0), T(0)}, T2{T(0), T(0)}};
-        if (y < g.n2) {
-          r.a = A[a_index(g, fa, kz, x, y)];
-          if (fb >= 0) r.b = A[a_index(g, fb, kz, x, y)];
-        }
-        return r;
-      },
-      [&](int, int kz, int yl, const Pair& r) { store_pair_values(r.a, r.b, kz, yl, n3, line, lstride); });
 }
 
 // The half spectra of one field pair for a z-pass tile, held in registers so that the next pair's
@@ -1073,45 +937,6 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __res
         dedsig[idx] = vs * invN;
       }
     }
-  }
-}
-
-// ---- pass 5 for plain real fields: out[f] = IFFT/N ---------------------------------------------
-
-template <typename T, int EPT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VDWXC_WPE_REALZI)))
-k_real_zinv(const typename Cx<T>::type* __restrict__ A, int nf, double* __restrict__ out,
-            const typename Cx<T>::type* __restrict__ tw, Geometry g, AxisPlan zp, int ty, int lstride) {
-  using T2 = typename Cx<T>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
-  const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
-  T2* line = reinterpret_cast<T2*>(smem);
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  int tile, x;
-  zpass_block(tile, x);
-  const int y0 = tile * ty;
-  const int n3 = g.n3;
-  const size_t N = size_t(g.n1) * g.n2 * n3;
-  const double invN = 1.0 / double(N);
-  const int npts = ty * n3;
-#pragma unroll 1
-  for (int fa = 0; fa < nf; fa += 2) {
-    const int fb = fa + 1 < nf ? fa + 1 : -1;
-    load_pair_line(A, g, fa, fb, x, y0, ty, line, lstride, tid, nthr);
-    __syncthreads();
-    lds_fft<EPT, +1>(line, zp, ty, lstride, twl, tid, nthr);
-    DivModStep it(tid, nthr, n3);
-    for (int e = tid; e < npts; e += nthr, it.next()) {
-      const int yl = it.q, z = it.r, y = y0 + yl;
-      if (y < g.n2) {
-        const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-        const T2 v = line[yl * lstride + lidx<>(z)];
-        out[size_t(fa) * N + idx] = double(v.x) * invN;
-        if (fb >= 0) out[size_t(fb) * N + idx] = double(v.y) * invN;
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -1364,6 +1189,175 @@ k_div_x(const T* __restrict__ in, double* __restrict__ v, const typename Cx<T>::
           v[(size_t(x) * n2 + y) * n3 + z0 + zl] = old - double(div);
         }
       });
+}
+
+// ---- spectral gradient, one axis at a time ----------------------------------------------------
+// The same factorisation gives the gradient of n (every Nyquist frequency dropped):
+// g_c = sum_i b_i,c d_i with d_x = P_y P_z D_x n, d_y = P_x P_z D_y n, d_z = P_x P_y D_z n, in
+// three passes:
+//   z: a = D_z n,  q = P_z n
+//   y: a' = P_y a,  b = D_y q,  q' = P_y q
+//   x: d_z = P_x a',  d_y = P_x b,  d_x = D_x q';  g_c = sum_i b_i,c d_i
+
+// z pass.  Block: `ty` y lines of one x plane (the z-pass block order).  in: n; out: [a, q].
+template <typename T, int EPT>
+__global__ void __launch_bounds__(512)
+k_grad_z(const double* __restrict__ nin, T* __restrict__ out, const typename Cx<T>::type* __restrict__ tw,
+         Geometry g, AxisPlan zp, int ty, int lstride) {
+  using T2 = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n3);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n3, threadIdx.x, blockDim.x);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  int tile, x;
+  zpass_block(tile, x);
+  const int y0 = tile * ty, n3 = g.n3;
+  const size_t N = size_t(g.n1) * g.n2 * n3;
+  const int nd = (ty + 1) >> 1, npts = ty * n3;
+  T2* pl = reinterpret_cast<T2*>(smem);     // line j: n of yl = 2j, 2j+1 (for the projection)
+  T2* dl = pl + size_t(nd) * lstride;        // the same values (for the derivative)
+  T2* csum = dl + size_t(nd) * lstride;
+  gather_strided_dm<kDivU>(
+      tid, nthr, npts, n3,
+      [&](int, int yl, int z) {
+        const int y = y0 + yl;
+        return y < g.n2 ? nin[(size_t(x) * g.n2 + y) * n3 + z] : 0.0;
+      },
+      [&](int, int yl, int z, double v) {
+        T* pp = reinterpret_cast<T*>(pl + (yl >> 1) * lstride + lidx<>(z));
+        T* dd = reinterpret_cast<T*>(dl + (yl >> 1) * lstride + lidx<>(z));
+        pp[yl & 1] = dd[yl & 1] = T(v);
+        if (!(yl & 1) && yl + 1 == ty) pp[1] = dd[1] = T(0);   // odd tile: the last pair has one member
+      });
+  __syncthreads();
+  project_and_derive<EPT>(pl, nd, dl, nd, csum, lstride, zp, twl, tid, nthr);
+  DivModStep it(tid, nthr, n3);
+  for (int e = tid; e < npts; e += nthr, it.next()) {
+    const int yl = it.q, z = it.r, y = y0 + yl;
+    if (y < g.n2) {
+      const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
+      const T2 pv = pl[(yl >> 1) * lstride + lidx<>(z)], c = csum[yl >> 1];
+      const T2 d = dl[(yl >> 1) * lstride + lidx<>(z)];
+      const T sg = (z & 1) ? T(-1) : T(1);
+      out[idx] = (yl & 1) ? d.y : d.x;
+      out[N + idx] = (yl & 1) ? pv.y - sg * c.y : pv.x - sg * c.x;
+    }
+  }
+}
+
+// y pass.  Block: `tz` consecutive z of one x plane (grid: z tiles x n1, XCD-aware order).
+// in: [a, q]; out: [a', b, q'].
+template <typename T, int EPT>
+__global__ void __launch_bounds__(512)
+k_grad_y(const T* __restrict__ in, T* __restrict__ out, const typename Cx<T>::type* __restrict__ tw, Geometry g,
+         AxisPlan yp, int tz, int lstride) {
+  using T2 = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n2);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n2, threadIdx.x, blockDim.x);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = xcd_logical_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int z0 = (L % gridDim.x) * tz, x = L / gridDim.x;
+  const int n2 = g.n2, n3 = g.n3;
+  const size_t N = size_t(g.n1) * n2 * n3;
+  const int nd = (tz + 1) >> 1, tot = tz * n2;
+  T2* pl = reinterpret_cast<T2*>(smem);     // line zl: (a, q)
+  T2* dl = pl + size_t(tz) * lstride;        // line j: (q of zl = 2j, 2j+1)
+  T2* csum = dl + size_t(nd) * lstride;
+  struct In {
+    T a, q;
+  };
+  gather_strided_dm<kDivU>(
+      tid, nthr, tot, tz,
+      [&](int, int y, int zl) {
+        In r{T(0), T(0)};
+        if (z0 + zl < n3) {
+          const size_t idx = (size_t(x) * n2 + y) * n3 + z0 + zl;
+          r.a = in[idx];
+          r.q = in[N + idx];
+        }
+        return r;
+      },
+      [&](int, int y, int zl, const In& r) {
+        pl[zl * lstride + lidx<>(y)] = T2{r.a, r.q};
+        T* d = reinterpret_cast<T*>(dl + (zl >> 1) * lstride + lidx<>(y));
+        d[zl & 1] = r.q;
+        if (!(zl & 1) && zl + 1 == tz) d[1] = T(0);
+      });
+  __syncthreads();
+  project_and_derive<EPT>(pl, tz, dl, nd, csum, lstride, yp, twl, tid, nthr);
+  DivModStep it(tid, nthr, tz);
+  for (int e = tid; e < tot; e += nthr, it.next()) {
+    const int y = it.q, zl = it.r;
+    if (z0 + zl < n3) {
+      const size_t idx = (size_t(x) * n2 + y) * n3 + z0 + zl;
+      const T2 p = pl[zl * lstride + lidx<>(y)], c = csum[zl];
+      const T2 d = dl[(zl >> 1) * lstride + lidx<>(y)];
+      const T sg = (y & 1) ? T(-1) : T(1);
+      out[idx] = p.x - sg * c.x;
+      out[N + idx] = (zl & 1) ? d.y : d.x;
+      out[2 * N + idx] = p.y - sg * c.y;
+    }
+  }
+}
+
+// x pass.  Block: `tz` consecutive z of one y (grid: z tiles x n2, XCD-aware order).
+// in: [a', b, q']; out: the gradient [3][N] in FP64.
+template <typename T, int EPT>
+__global__ void __launch_bounds__(512)
+k_grad_x(const T* __restrict__ in, double* __restrict__ gout, const typename Cx<T>::type* __restrict__ tw,
+         Geometry g, AxisPlan xp, int tz, int lstride) {
+  using T2 = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n1);
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n1, threadIdx.x, blockDim.x);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = xcd_logical_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int z0 = (L % gridDim.x) * tz, y = L / gridDim.x;
+  const int n1 = g.n1, n2 = g.n2, n3 = g.n3;
+  const size_t N = size_t(n1) * n2 * n3;
+  const int nd = (tz + 1) >> 1, tot = tz * n1;
+  T2* pl = reinterpret_cast<T2*>(smem);     // line zl: (a', b)
+  T2* dl = pl + size_t(tz) * lstride;        // line j: (q' of zl = 2j, 2j+1)
+  T2* csum = dl + size_t(nd) * lstride;
+  struct In {
+    T a, b, q;
+  };
+  gather_strided_dm<kDivU>(
+      tid, nthr, tot, tz,
+      [&](int, int x, int zl) {
+        In r{T(0), T(0), T(0)};
+        if (z0 + zl < n3) {
+          const size_t idx = (size_t(x) * n2 + y) * n3 + z0 + zl;
+          r.a = in[idx];
+          r.b = in[N + idx];
+          r.q = in[2 * N + idx];
+        }
+        return r;
+      },
+      [&](int, int x, int zl, const In& r) {
+        pl[zl * lstride + lidx<>(x)] = T2{r.a, r.b};
+        T* d = reinterpret_cast<T*>(dl + (zl >> 1) * lstride + lidx<>(x));
+        d[zl & 1] = r.q;
+        if (!(zl & 1) && zl + 1 == tz) d[1] = T(0);
+      });
+  __syncthreads();
+  project_and_derive<EPT>(pl, tz, dl, nd, csum, lstride, xp, twl, tid, nthr);
+  DivModStep it(tid, nthr, tz);
+  for (int e = tid; e < tot; e += nthr, it.next()) {
+    const int x = it.q, zl = it.r;
+    if (z0 + zl < n3) {
+      const size_t idx = (size_t(x) * n2 + y) * n3 + z0 + zl;
+      const T2 p = pl[zl * lstride + lidx<>(x)], c = csum[zl];
+      const T2 d = dl[(zl >> 1) * lstride + lidx<>(x)];
+      const T sg = (x & 1) ? T(-1) : T(1);
+      const double dz = double(p.x - sg * c.x), dy = double(p.y - sg * c.y);
+      const double dx = double((zl & 1) ? d.y : d.x);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        gout[size_t(cc) * N + idx] = g.bvec[cc] * dx + g.bvec[3 + cc] * dy + g.bvec[6 + cc] * dz;
+    }
+  }
 }
 
 }  // namespace vdwxc

@@ -33,10 +33,6 @@ template <typename T>
 constexpr int asm_pb() { return sizeof(T) == 8 ? 2 : 1; }
 constexpr int kEPTA = 4;         // grid points (and FFT elements) per thread in the z assembly
 constexpr int kEPT = 8;          // FFT elements per thread in the z and y passes
-#ifndef VDWXC_EPTX
-#define VDWXC_EPTX 8
-#endif
-constexpr int kEPTX = VDWXC_EPTX;  // FFT elements per thread in the spectral x passes
 #ifndef VDWXC_EPTC
 #define VDWXC_EPTC 20
 #endif
@@ -78,8 +74,9 @@ struct vdwxc_ctx {
   int device = 0;
   Geometry geo{};
   AxisPlan plan[3]{};
-  Launch zl64, zl32, za64, za32, yl64, yl32, xl64, xl32, xs64;   // xs: gradient x pass (FP64)
+  Launch zl64, zl32, za64, za32, yl64, yl32, xl64, xl32;
   Launch dz64, dz32, dy64, dy32, dx64, dx32;   // divergence passes (lds: the whole block)
+  Launch gz, gy, gx;                           // gradient passes, FP64 (lds: the whole block)
   size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
   bool x_capped = false;   // launch the register-capped contraction kernel
   bool ortho = false;
@@ -266,18 +263,6 @@ bool line_launch(int maxt, int n, int other, size_t cplx_bytes, Launch& L, int e
 }
 
 
-bool xline_launch(int nlines, int n, int slots, size_t cplx_bytes, Launch& L) {
-  // all field lines of one column in LDS, transformed in groups of nthr * EPT / n lines; one
-  // thread per contraction slot up to kMaxThreadsX
-  L.tile = nlines;
-  L.nthr = std::min(kMaxThreadsX, std::max(64, round_up(slots, 64)));
-  if (n > L.nthr * kEPTX || n > kMaxAxis) return false;
-  L.lstride = lds_span<>(n);
-  L.lds = ((size_t(n) * cplx_bytes + 15) & ~size_t(15)) +
-          std::max<size_t>(size_t(nlines) * L.lstride * cplx_bytes, 16 * sizeof(double));
-  return L.lds <= kMaxLds;
-}
-
 template <typename T>
 size_t zstate_lds(const Launch& L, int n3, int per_point_values) {
   const size_t npts = size_t(L.tile) * n3;
@@ -350,25 +335,23 @@ bool pick_ztile(K* kernel, int n3, int other, int values, int ept, Launch& out, 
   return pick_occupancy(kernel, c, nc, out, lds_out);
 }
 
-// Divergence passes (k_div_z / _y / _x): `tile` lines of the axis (length n) per block, held as
-// plines "P lines" and dlines "D lines" (complex, two real series each) plus one complex sum per
-// P line.  The z pass tiles y lines like the other z passes (tiles halve from min(kLineTile,
-// n2)); the y and x passes tile z in powers of two from min(16, n3 rounded up), at least 2.  The
-// chosen launch's L.lds is the block's whole LDS.
-int div_plines(int axis, int tile) { return axis == 0 ? (tile + 1) / 2 : tile; }
-
+// One-axis passes of the divergence and gradient (k_div_*, k_grad_*): `tile` lines of the axis
+// (length n) per block, held as np "P lines" and nd = ceil(tile / 2) "D lines" (complex, two real
+// series each) plus one complex sum per P line; np = ceil(tile / 2) when the P lines pack pairs
+// (p_half), else tile.  z passes (zpass) tile y lines like the other z passes (tiles halve from
+// min(kLineTile, n2) down to 1); y and x passes tile z in powers of two from min(16, n3 rounded
+// up), at least 2.  The chosen launch's L.lds is the block's whole LDS.
 template <typename T, typename K>
-bool pick_div(K* kernel, int axis, int n, int first_tile, Launch& out) {
+bool pick_div(K* kernel, bool zpass, bool p_half, int n, int first_tile, Launch& out) {
   const size_t cplx = 2 * sizeof(T);
   Cand c[8];
   int nc = 0;
-  const int last = axis == 2 ? 1 : 2;
-  for (int tile = first_tile; tile >= last && nc < 8; tile /= 2) {
-    const int np = div_plines(axis, tile), nd = (tile + 1) / 2;
-    if (long(nd) * n > long(kMaxThreadsZ) * kEPT || n > kMaxAxis) continue;
+  for (int tile = first_tile; tile >= (zpass ? 1 : 2) && nc < 8; tile /= 2) {
+    const int nd = (tile + 1) / 2, np = p_half ? nd : tile;
+    if (long(zpass ? tile : nd) * n > long(kMaxThreadsZ) * kEPT || n > kMaxAxis) continue;
     Launch L;
     L.tile = tile;
-    L.nthr = threads_for(long(std::max(np, nd)) * n, kEPT, kMaxThreadsZ);
+    L.nthr = threads_for(long(zpass ? tile : std::max(np, nd)) * n, kEPT, kMaxThreadsZ);
     if (nc > 0 && L.nthr < 128) break;
     L.lstride = lds_span<>(n) | 1;
     L.lds = tw_lds_bytes<typename Cx<T>::type>(n) + size_t(np + nd) * L.lstride * cplx + size_t(np) * cplx;
@@ -438,7 +421,6 @@ template <> struct Prec<double> {
   static const Launch& za(const vdwxc_ctx* h) { return h->za64; }
   static const Launch& y(const vdwxc_ctx* h) { return h->yl64; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
-  static const Launch& xs(const vdwxc_ctx* h) { return h->xs64; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz64 : a == 1 ? h->dy64 : h->dx64; }
   static const double2* tw(const vdwxc_ctx* h, int a) { return h->d_tw64[a]; }
   static const Quad<double>* table(const vdwxc_ctx* h) { return h->d_table64; }
@@ -500,32 +482,24 @@ void enqueue_ypass(vdwxc_ctx* h, int nf, int dir, int stage) {
   stage_end(h, stage);
 }
 
-// spectral gradient of the FP64 density n: forward z, y, x; i G_c on the x pass (1 -> 3 fields);
-// inverse x, y, z into out[3][N]
-template <typename T>
+// spectral gradient of the FP64 density n into out ([3][N], FP64), one axis at a time
+// (k_grad_z, k_grad_y, k_grad_x); the intermediate real fields sit in the work buffers ([2][N] in
+// A, [3][N] in B), in FP64 whatever the handle's precision, because the gradient feeds q0
 void enqueue_gradient(vdwxc_ctx* h, const double* src, double* out) {
-  using T2 = typename Cx<T>::type;
-  const Launch& Lz = Prec<T>::z(h);
-  const Launch& Lx = Prec<T>::xs(h);
-  T2* A = static_cast<T2*>(h->d_A);
-  T2* B = static_cast<T2*>(h->d_B);
-  Geometry g = h->geo;
-  g.M = 1;
-  dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
+  double* F2 = static_cast<double*>(h->d_A);
+  double* F3 = static_cast<double*>(h->d_B);
   stage_begin(h);
-  hipLaunchKernelGGL((k_real_zfwd<T, kEPT>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, src, 1, A, Prec<T>::tw(h, 2),
-                     g, h->plan[2], Lz.tile, Lz.lstride);
+  hipLaunchKernelGGL((k_grad_z<double, kEPT>), dim3((h->n2 + h->gz.tile - 1) / h->gz.tile, h->n1), dim3(h->gz.nthr),
+                     h->gz.lds, h->stream, src, F2, h->d_tw64[2], h->geo, h->plan[2], h->gz.tile, h->gz.lstride);
   stage_end(h, VDWXC_STAGE_GRAD_Z);
-  enqueue_ypass<T>(h, 1, -1, VDWXC_STAGE_GRAD_Y);
   stage_begin(h);
-  hipLaunchKernelGGL((k_xgradient<T, kEPTX>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
-                     Prec<T>::tw(h, 0), g, h->plan[0]);
+  hipLaunchKernelGGL((k_grad_y<double, kEPT>), dim3((h->n3 + h->gy.tile - 1) / h->gy.tile, h->n1), dim3(h->gy.nthr),
+                     h->gy.lds, h->stream, F2, F3, h->d_tw64[1], h->geo, h->plan[1], h->gy.tile, h->gy.lstride);
+  stage_end(h, VDWXC_STAGE_GRAD_Y);
+  stage_begin(h);
+  hipLaunchKernelGGL((k_grad_x<double, kEPT>), dim3((h->n3 + h->gx.tile - 1) / h->gx.tile, h->n2), dim3(h->gx.nthr),
+                     h->gx.lds, h->stream, F3, out, h->d_tw64[0], h->geo, h->plan[0], h->gx.tile, h->gx.lstride);
   stage_end(h, VDWXC_STAGE_GRAD_X);
-  enqueue_ypass<T>(h, 3, +1, VDWXC_STAGE_GRAD_YI);
-  stage_begin(h);
-  hipLaunchKernelGGL((k_real_zinv<T, kEPT>), zgrid, dim3(Lz.nthr), Lz.lds, h->stream, A, 3, out, Prec<T>::tw(h, 2),
-                     g, h->plan[2], Lz.tile, Lz.lstride);
-  stage_end(h, VDWXC_STAGE_GRAD_ZI);
 }
 
 // v -= spectral divergence of 2 S grad n, one axis at a time (k_div_z, k_div_y, k_div_x); the
@@ -623,7 +597,7 @@ vdwxc_status run_potential(vdwxc_ctx* h, const double* n, const double* grad, do
   const double* g = grad;
   if (!g) {
     // the gradient feeds q0, so it is taken in FP64 in both precisions
-    enqueue_gradient<double>(h, n, h->d_G);
+    enqueue_gradient(h, n, h->d_G);
     g = h->d_G;
   }
   if (h->precision == VDWXC_FP64) {
@@ -751,8 +725,7 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     return fail(nullptr, VDWXC_EINVAL, "grid reaches |G| >= kmax of the kernel table (grid too fine)");
   }
   bool ok = line_launch(kMaxThreadsZ, h->n3, h->n2, 16, h->zl64) && line_launch(kMaxThreadsZ, h->n3, h->n2, 8, h->zl32) &&
-            line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64) && line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32) &&
-            xline_launch(3, h->n1, h->n1, 16, h->xs64);
+            line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64) && line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32);
   {
     // contraction pass: one thread per k-point up to kMaxThreadsX (the kernel strides beyond)
     Launch& L = precision == VDWXC_FP64 ? h->xl64 : h->xl32;
@@ -899,12 +872,18 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     set_lds_limit(k_div_z<float, kEPT>, kMaxLds);
     set_lds_limit(k_div_y<float, kEPT>, kMaxLds);
     set_lds_limit(k_div_x<float, kEPT>, kMaxLds);
-    if (!pick_div<double>(k_div_z<double, kEPT>, 2, h->n3, yt, h->dz64) ||
-        !pick_div<double>(k_div_y<double, kEPT>, 1, h->n2, zt, h->dy64) ||
-        !pick_div<double>(k_div_x<double, kEPT>, 0, h->n1, zt, h->dx64) ||
-        !pick_div<float>(k_div_z<float, kEPT>, 2, h->n3, yt, h->dz32) ||
-        !pick_div<float>(k_div_y<float, kEPT>, 1, h->n2, zt, h->dy32) ||
-        !pick_div<float>(k_div_x<float, kEPT>, 0, h->n1, zt, h->dx32)) {
+    set_lds_limit(k_grad_z<double, kEPT>, kMaxLds);
+    set_lds_limit(k_grad_y<double, kEPT>, kMaxLds);
+    set_lds_limit(k_grad_x<double, kEPT>, kMaxLds);
+    if (!pick_div<double>(k_div_z<double, kEPT>, true, false, h->n3, yt, h->dz64) ||
+        !pick_div<double>(k_div_y<double, kEPT>, false, false, h->n2, zt, h->dy64) ||
+        !pick_div<double>(k_div_x<double, kEPT>, false, true, h->n1, zt, h->dx64) ||
+        !pick_div<float>(k_div_z<float, kEPT>, true, false, h->n3, yt, h->dz32) ||
+        !pick_div<float>(k_div_y<float, kEPT>, false, false, h->n2, zt, h->dy32) ||
+        !pick_div<float>(k_div_x<float, kEPT>, false, true, h->n1, zt, h->dx32) ||
+        !pick_div<double>(k_grad_z<double, kEPT>, true, true, h->n3, yt, h->gz) ||
+        !pick_div<double>(k_grad_y<double, kEPT>, false, false, h->n2, zt, h->gy) ||
+        !pick_div<double>(k_grad_x<double, kEPT>, false, false, h->n1, zt, h->gx)) {
       release(h);
       return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
     }
@@ -917,8 +896,6 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_theta_zfwd<float, kEPT, true>, h->lds_theta32);
   set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA, asm_pb<double>()>, h->lds_asm64);
   set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA, asm_pb<float>()>, h->lds_asm32);
-  set_lds_limit(k_real_zfwd<double, kEPT>, h->zl64.lds);
-  set_lds_limit(k_real_zinv<double, kEPT>, h->zl64.lds);
   set_lds_limit(k_ypass<double, kEPT, -1>, h->yl64.lds);
   set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
@@ -926,7 +903,9 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_xcontract<double, kEPTC, kXPad, 1>, h->xl64.lds);
   set_lds_limit(k_xcontract<float, kEPTC, kXPad, 1>, h->xl32.lds);
   set_lds_limit(k_xcontract<float, kEPTC, kXPad, 4>, h->xl32.lds);
-  set_lds_limit(k_xgradient<double, kEPTX>, h->xs64.lds);
+  set_lds_limit(k_grad_z<double, kEPT>, h->gz.lds);
+  set_lds_limit(k_grad_y<double, kEPT>, h->gy.lds);
+  set_lds_limit(k_grad_x<double, kEPT>, h->gx.lds);
   set_lds_limit(k_div_z<double, kEPT>, h->dz64.lds);
   set_lds_limit(k_div_y<double, kEPT>, h->dy64.lds);
   set_lds_limit(k_div_x<double, kEPT>, h->dx64.lds);
@@ -1001,7 +980,7 @@ vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const do
 const char* vdwxc_stage_name(int stage) {
   static const char* names[VDWXC_NUM_STAGES] = {
       "theta_zfwd", "y_fwd", "x_contract", "y_inv", "z_assemble", "grad_z", "grad_y",
-      "grad_x", "grad_yi", "grad_zi", "div_z", "div_y", "div_x"};
+      "grad_x", "div_z", "div_y", "div_x"};
   return (stage >= 0 && stage < VDWXC_NUM_STAGES) ? names[stage] : "?";
 }
 

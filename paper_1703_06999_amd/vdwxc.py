@@ -49,7 +49,7 @@ SIGNATURES = {
     "vdwxc_read_timing": (ctypes.c_int, [_h, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "vdwxc_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
 }
-NUM_STAGES = 13
+NUM_STAGES = 11
 
 _lib = None
 
