@@ -99,6 +99,30 @@ class Server:
         self.peak_resident = max(self.peak_resident, self.resident)
         return h
 
+    def warm(self, shapes):
+        """Create every slot's handle for each (grid, cell) in `shapes` ahead of traffic, as far as
+        the HBM budget allows (plans, tables and work buffers then stay resident), so that no
+        request pays for a handle's set-up.  Returns the number of handles created."""
+        made = 0
+        for grid, cell in shapes:
+            probe = Request(-1, tuple(grid), np.asarray(cell, dtype=np.float64), None)
+            for slot in self.slots:
+                key = self._key(probe)
+                if key in slot.handles:
+                    continue
+                need = self._cost(probe.grid)
+                if self.resident + need > self.budget:
+                    return made
+                with torch.cuda.stream(slot.stream):
+                    slot.handles[key] = vdwxc.Functional(probe.grid, probe.cell, flavour=self.flavour,
+                                                         precision=self.precision, table=self.table,
+                                                         stream=slot.stream)
+                self.resident += need
+                self.peak_resident = max(self.peak_resident, self.resident)
+                made += 1
+        torch.cuda.synchronize()
+        return made
+
     # ---- scheduling --------------------------------------------------------------------------
     def submit(self, req: Request):
         self.queue.append(req)
@@ -179,6 +203,16 @@ class Server:
                 h.close()
             s.handles.clear()
         self.resident = 0.0
+
+
+def serving_shapes(grids=(48, 64, 96, 128, 160)):
+    """The (grid, cell) pairs of the serving workload, for Server.warm."""
+    from . import inputs
+    out = []
+    for g in grids:
+        w = inputs.workload("serving", grid_n=int(g))
+        out.append((w.grid, w.cell))
+    return out
 
 
 def poisson_requests(count: int, rate: float, seed: int, device="cuda", grids=(48, 64, 96, 128, 160)):

@@ -168,6 +168,32 @@ def test_serving_admission_under_small_budget(dev):
         assert float(r.energy.item()) == E and torch.equal(r.v, v)
 
 
+def test_serving_warm_handles(dev):
+    """Handles created ahead of traffic: every slot gets one per shape while the budget lasts,
+    the budget is never exceeded, no request creates another, and the results are the same bits."""
+    from paper_1703_06999_amd import serving, vdwxc
+    say("[serving warm]")
+    reqs = _small_requests(12, rate=3000.0, seed=4, grids=(16, 24))
+    shapes = [((g, g, g), inputs.cubic_cell(g * 0.3)) for g in (16, 24)]
+    srv = serving.Server(KT, slots=3, precision="fp32")
+    assert srv.warm(shapes) == 6
+    assert srv.warm(shapes) == 0                       # already resident
+    before = {s.index: set(s.handles) for s in srv.slots}
+    summary = srv.run(reqs)
+    assert {s.index: set(s.handles) for s in srv.slots} == before
+    srv.close()
+    say(f"    {summary}")
+    assert summary["requests"] == len(reqs)
+    for r in reqs:
+        E, v = _alone(r, "fp32")
+        assert float(r.energy.item()) == E and torch.equal(r.v, v), r.rid
+    small = serving.Server(KT, slots=3, precision="fp32",
+                           hbm_budget=2.5 * vdwxc.workspace_bytes((24, 24, 24), "fp32", KT.nq))
+    made = small.warm(shapes)
+    assert 1 <= made < 6 and small.peak_resident <= small.budget
+    small.close()
+
+
 def test_serving_results_match_oracle(dev):
     from paper_1703_06999_amd import serving
     say("[serving vs oracle]")
