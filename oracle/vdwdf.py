@@ -45,6 +45,8 @@ from __future__ import annotations
 
 import math
 import os
+import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import scipy.fft as sfft
@@ -60,7 +62,32 @@ SATURATION_A = 5.0
 SATURATION_TERMS = 12
 VACUUM_DENSITY = 1e-30
 
-WORKERS = os.cpu_count() or 1
+
+def _workers():
+    """scipy.fft worker threads: the host's cores available to this process, capped by
+    OMP_NUM_THREADS when that is set (on a shared host it names this process's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+WORKERS = _workers()
+
+
+def _map_chunks(fn, count, chunk):
+    """[fn(s, e) for consecutive ranges [s, e) of `chunk` items covering range(count)], the calls
+    spread over WORKERS threads (numpy releases the GIL inside its loops).  The ranges are
+    independent; the results come back in range order."""
+    ranges = [(s, min(s + chunk, count)) for s in range(0, count, chunk)]
+    if WORKERS <= 1 or len(ranges) <= 1:
+        return [fn(s, e) for s, e in ranges]
+    with ThreadPoolExecutor(max_workers=WORKERS) as pool:
+        return list(pool.map(lambda r: fn(*r), ranges))
 
 
 # ---------------------------------------------------------------------------------------------
@@ -192,16 +219,28 @@ def spline_values(qmesh, coeffs, q0):
 def theta_and_derivatives(n, sigma, qmesh, zab):
     """theta_a = n p_a(q0) (Sec. 2) and the factors of the partial derivatives (eqs. dedn,
     dedsigma):  dtheta_a/dn = p_a + n p_a' dq0/dn,  dtheta_a/dsigma = n p_a' dq0/dsigma.
-    Vacuum points carry zeros.  Arrays [M][N1][N2][N3]."""
+    Vacuum points carry zeros.  Arrays [M][N1][N2][N3].  Every point is independent of the others;
+    the points are taken in chunks on the worker threads."""
     n = np.asarray(n, dtype=np.float64)
+    sigma = np.broadcast_to(np.asarray(sigma, dtype=np.float64), n.shape)
     coeffs = spline_coefficients(qmesh)
-    q0, dq_dn, dq_ds, vac = q0_and_derivatives(n, sigma, qmesh, zab)
-    p, dp = spline_values(qmesh, coeffs, q0)
-    nn = np.where(vac, 0.0, n)
-    theta = nn * p
-    dtheta_dn = np.where(vac, 0.0, p + nn * dp * dq_dn)
-    dtheta_ds = nn * dp * dq_ds
-    return theta, dtheta_dn, dtheta_ds
+    M = len(qmesh)
+    nf, sf = n.reshape(-1), np.ascontiguousarray(sigma).reshape(-1)
+    theta = np.empty((M, nf.size))
+    dtheta_dn = np.empty((M, nf.size))
+    dtheta_ds = np.empty((M, nf.size))
+
+    def points(s, e):
+        q0, dq_dn, dq_ds, vac = q0_and_derivatives(nf[s:e], sf[s:e], qmesh, zab)
+        p, dp = spline_values(qmesh, coeffs, q0)
+        nn = np.where(vac, 0.0, nf[s:e])
+        theta[:, s:e] = nn * p
+        dtheta_dn[:, s:e] = np.where(vac, 0.0, p + nn * dp * dq_dn)
+        dtheta_ds[:, s:e] = nn * dp * dq_ds
+
+    _map_chunks(points, nf.size, 1 << 16)
+    shape = (M,) + n.shape
+    return theta.reshape(shape), dtheta_dn.reshape(shape), dtheta_ds.reshape(shape)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -284,19 +323,23 @@ def interpolate_kernel(table, kmax, knorm):
     return np.where(inside[:, None, None], phi, 0.0)
 
 
-def kspace_contraction(theta_k, knorm, table, kmax, chunk=1 << 16):
+def kspace_contraction(theta_k, knorm, table, kmax, chunk=2048):
     """F_a(m) = sum_b phi_ab(|G_m|) theta_b(m) and the energy sum sum_m sum_a Re[theta_a* F_a]
     (Sec. 3, steps 3a-3c).  theta_k: [M][...] complex; returns (F_k, energy_sum)."""
     M = theta_k.shape[0]
     th = theta_k.reshape(M, -1)
     kn = knorm.reshape(-1)
     F = np.empty_like(th)
+
+    def kpoints(s, e):
+        phi = interpolate_kernel(table, kmax, kn[s:e])      # [c][a][b]
+        f = np.einsum("cab,bc->ac", phi, th[:, s:e])
+        F[:, s:e] = f
+        return float(np.sum((np.conj(th[:, s:e]) * f).real))
+
     esum = 0.0
-    for s in range(0, kn.shape[0], chunk):
-        phi = interpolate_kernel(table, kmax, kn[s:s + chunk])      # [c][a][b]
-        f = np.einsum("cab,bc->ac", phi, th[:, s:s + chunk])
-        F[:, s:s + chunk] = f
-        esum += float(np.sum((np.conj(th[:, s:s + chunk]) * f).real))
+    for part in _map_chunks(kpoints, kn.shape[0], chunk):   # the chunks' sums in chunk order
+        esum += part
     return F.reshape(theta_k.shape), esum
 
 
@@ -318,9 +361,26 @@ def check_inputs(grid, cell, n, sigma):
         raise ValueError("density or sigma contains NaN/inf")
 
 
-def energy_and_partials(n, sigma, cell, kernel, flavour="DF1", return_intermediates=False):
+class _Steps:
+    """Calls ``progress(step_name, seconds)`` after each step, if a callback is given (timing and
+    progress reports only; nothing here touches the arithmetic)."""
+
+    def __init__(self, progress):
+        self.progress = progress
+        self.t = time.perf_counter()
+
+    def done(self, name):
+        if self.progress is not None:
+            now = time.perf_counter()
+            self.progress(name, now - self.t)
+            self.t = now
+
+
+def energy_and_partials(n, sigma, cell, kernel, flavour="DF1", return_intermediates=False, progress=None):
     """E_c^nl and the partial derivatives dE/dn, dE/dsigma as fields (Sec. 2, eqs. dedn and
-    dedsigma; Sec. 3 procedure).  Returns (E, dedn, dedsigma[, dict])."""
+    dedsigma; Sec. 3 procedure).  Returns (E, dedn, dedsigma[, dict]).  ``progress``, if given, is
+    called as progress(step, seconds) after each step."""
+    steps = _Steps(progress)
     n = np.asarray(n, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
     grid = n.shape
@@ -333,12 +393,17 @@ def energy_and_partials(n, sigma, cell, kernel, flavour="DF1", return_intermedia
         raise ValueError("grid reaches |G| >= kmax of the kernel table")
 
     theta, dth_dn, dth_ds = theta_and_derivatives(n, sigma, qmesh, ZAB[flavour])   # step 1
+    steps.done("q0 + theta")
     theta_k = forward_fft(theta)                                                    # step 2
+    steps.done("forward FFT")
     F_k, esum = kspace_contraction(theta_k, knorm, table, kmax)                    # step 3
+    steps.done("contraction")
     E = omega / (2.0 * N * N) * esum
     F = inverse_fft(F_k)                                                            # step 4
+    steps.done("inverse FFT")
     dedn = np.sum(F * dth_dn, axis=0)                                               # step 5
     dedsigma = np.sum(F * dth_ds, axis=0)
+    steps.done("derivatives")
     if return_intermediates:
         return E, dedn, dedsigma, dict(theta=theta, theta_k=theta_k, F_k=F_k, F=F,
                                        dtheta_dn=dth_dn, dtheta_dsigma=dth_ds, knorm=knorm)
@@ -365,13 +430,18 @@ def spectral_gradient(n, cell):
     return np.stack([spectral_derivative(n, cell, i) for i in range(3)])
 
 
-def potential(n, cell, kernel, grad=None, flavour="DF1"):
+def potential(n, cell, kernel, grad=None, flavour="DF1", progress=None):
     """v_c^nl = dE/dn|_sigma - div(2 dE/dsigma grad n)  (Sec. 2: v = dE/dn + dE/dsigma dsigma/dn,
     with sigma = |grad n|^2).  ``grad`` [3][...] is the supplied gradient; None means the
-    spectral gradient of n.  Returns (E, v, dedn, dedsigma)."""
+    spectral gradient of n.  Returns (E, v, dedn, dedsigma).  ``progress``: as in
+    energy_and_partials."""
+    steps = _Steps(progress)
     n = np.asarray(n, dtype=np.float64)
     g = spectral_gradient(n, cell) if grad is None else np.asarray(grad, dtype=np.float64)
     sigma = np.sum(g * g, axis=0)
-    E, dedn, dedsigma = energy_and_partials(n, sigma, cell, kernel, flavour)
+    steps.done("gradient" if grad is None else "sigma")
+    E, dedn, dedsigma = energy_and_partials(n, sigma, cell, kernel, flavour, progress=progress)
+    steps.t = time.perf_counter()
     div = sum(spectral_derivative(2.0 * dedsigma * g[i], cell, i) for i in range(3))
+    steps.done("divergence")
     return E, dedn - div, dedn, dedsigma
