@@ -1,20 +1,27 @@
 """Benchmark: grid points per second for one E_c^nl + v_c^nl evaluation (N_alpha = 20) on one GPU.
 
-    python bench.py [--steps K] [--warmup W] [--workload slater_128] [--precision fp32|fp64]
+    python bench.py [--steps K] [--warmup W] [--workload nanoparticle_512] [--precision fp64|fp32]
 
 A step is one potential evaluation (theta + forward FFTs, contraction, inverse FFTs, derivative
 assembly, spectral divergence, energy) of the workload's seeded synthetic density, with its
-analytic gradient, inputs already resident in HBM.  Prints one JSON line.  The K timed steps run
-twice: without instrumentation (value, ms_per_step), then with the library's HIP events around
-every kernel on its stream; the roofline figure is the dominant kernel's algorithmic bytes per
-launch over its average event-timed duration.  The CPU baseline is the FP64 oracle on the host
-cores, on the workload named in its "sample" field.
+analytic gradient, inputs already resident in HBM.  The headline is the 512^3 / 48 Angstrom
+nanoparticle (the largest workload; its 23.8 / 47 GB of work buffers fit one GPU) in FP64, the
+paper's arithmetic; the FP32_MIXED form on the same workload is reported under "fp32_mixed",
+with its difference to the FP64 result.  Prints one JSON line.
+
+The K timed steps run twice per form: without instrumentation (value, ms_per_step), then with
+the library's HIP events around every kernel on its stream; the roofline figure is the dominant
+kernel's algorithmic bytes per launch over its average event-timed duration.  The CPU baseline is
+the FP64 oracle on the host cores, on the bounded workload named in its "sample" field.  The
+serving measurement replays a Poisson stream of requests through the continuous-batching server
+in the FP32_MIXED form.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -23,6 +30,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 M = 20
+METRIC = "grid pts/s for E_c^nl+v_c^nl (Nalpha=20) at stated rel. error; p50/p99 serve latency"
+
+
+def say(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     from paper_1703_06999_amd.profiling import source_hash
     return source_hash()
@@ -71,30 +85,108 @@ def stage_bytes(stage: str, grid, precision: str, m: int = M) -> float:
     }.get(stage, 0.0)
 
 
+def host_description() -> dict:
+    """CPU model, logical CPUs usable by this process and RAM of the host."""
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram_gb = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                ram_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": cpus, "ram_GiB": ram_gb}
+
+
 def cpu_baseline(workload_name: str, n_cpu, g_cpu, w, kt):
-    """Time the FP64 oracle on the host for one evaluation; returns (record, oracle E, oracle v)."""
+    """Time the FP64 oracle on the host for one evaluation, stage by stage."""
     from oracle import vdwdf
+    stages = {}
+
+    def progress(step, dt):
+        stages[step] = round(stages.get(step, 0.0) + dt, 3)
     t0 = time.perf_counter()
-    E, v, _, _ = vdwdf.potential(n_cpu, w.cell, kt, grad=g_cpu)
+    vdwdf.potential(n_cpu, w.cell, kt, grad=g_cpu, progress=progress)
     dt = time.perf_counter() - t0
-    rec = {"value": w.npoints / dt, "unit": "grid pts/s", "cores": int(vdwdf.WORKERS), "kind": "oracle",
-           "sample": f"one FP64 E+v evaluation of {workload_name} ({w.grid[0]}x{w.grid[1]}x{w.grid[2]}), "
-                     f"{dt:.1f} s, scipy.fft with {vdwdf.WORKERS} workers"}
-    return rec, E, v
+    host = host_description()
+    return {"value": w.npoints / dt, "unit": "grid pts/s", "cores": int(vdwdf.WORKERS), "kind": "oracle",
+            "sample": f"one FP64 E+v evaluation (analytic gradient) of {workload_name} "
+                      f"({w.grid[0]}x{w.grid[1]}x{w.grid[2]}, {w.npoints} points), {dt:.1f} s; scipy.fft "
+                      f"with {vdwdf.WORKERS} worker threads, the other stages numpy on one thread",
+            "workload": workload_name, "seconds": round(dt, 3), "stage_seconds": stages, **host}
+
+
+def time_form(f, n, g, steps: int, warmup: int, grid, precision: str):
+    """Warm up, then time `steps` evaluations twice (plain, then with per-kernel HIP events).
+    Returns (ms_per_step, stages, roofline, v, E)."""
+    import torch
+    dev = n.device
+    v = torch.empty_like(n)
+    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        f.potential_async(n, g, v, e)
+    torch.cuda.synchronize()
+    # timed region 1: throughput, no instrumentation
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f.potential_async(n, g, v, e)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # timed region 2: the same steps with the library's per-kernel HIP events (recorded on the
+    # stream the kernels run on), for the per-kernel durations behind the roofline figure
+    f.enable_timing(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        f.potential_async(n, g, v, e)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    stages = f.read_timing()
+    f.enable_timing(False)
+    ms_per_step = 1e3 * (t1 - t0) / steps
+    per_stage = {k: {"ms_avg": round(ms / cnt, 4), "launches": cnt,
+                     "GBps": round(stage_bytes(k, grid, precision) / (ms / cnt * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(stage_bytes(k, grid, precision) / (ms / cnt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                 for k, (ms, cnt) in stages.items()}
+    dom = max(stages, key=lambda k: stages[k][0])
+    avg_s = stages[dom][0] / stages[dom][1] * 1e-3
+    achieved = stage_bytes(dom, grid, precision) / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes_per_launch": stage_bytes(dom, grid, precision),
+                "avg_launch_ms": round(avg_s * 1e3, 4),
+                "timing": "HIP events around each kernel over a second timed region of the same steps "
+                          f"({1e3 * (t3 - t2) / steps:.4f} ms/step with the events)"}
+    return ms_per_step, per_stage, roofline, v, float(e.item())
 
 
 def serving_measurement(kt, count, rate, precision):
     """Poisson stream of `count` energy+potential requests (grids 48..160^3) through the
-    continuous-batching server: once with a 64 GB HBM budget, once capped at 1 GB so admission
-    queues.  Densities are generated, and the slots' handles for the five shapes created (as far
-    as the budget allows), before the clock starts."""
+    continuous-batching server: once with a 64 GB HBM budget, once with the budget capped at 1.25x
+    the largest request's workspace, so that admission queues.  Densities are generated, and the
+    slots' handles for the five shapes created (as far as the budget allows), before the clock
+    starts."""
     import torch
 
-    from paper_1703_06999_amd import serving
-    print(f"[bench] serving: generating {count} requests", file=sys.stderr, flush=True)
+    from paper_1703_06999_amd import serving, vdwxc
+    say(f"serving: generating {count} requests")
     reqs = serving.poisson_requests(count, rate, seed=0)
-    res = {"requests": count, "rate_per_s": rate, "grids": [48, 64, 96, 128, 160], "precision": precision}
-    for label, budget in (("budget_64GB", 64e9), ("budget_1GB", 1e9)):
+    grids = [48, 64, 96, 128, 160]
+    small = 1.25 * vdwxc.workspace_bytes((160, 160, 160), precision)
+    res = {"requests": count, "rate_per_s": rate, "grids": grids, "precision": precision}
+    for label, budget in (("budget_64GB", 64e9), (f"budget_{small / 1e9:.2f}GB", small)):
         for r in reqs:
             r.admitted = r.finished = r.energy = r.v = None
         srv = serving.Server(kt, slots=4, precision=precision, hbm_budget=budget)
@@ -104,18 +196,22 @@ def serving_measurement(kt, count, rate, precision):
         srv.close()
         torch.cuda.empty_cache()
         res[label] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summary.items()}
-        print(f"[bench] serving {label}: {res[label]}", file=sys.stderr, flush=True)
+        say(f"serving {label}: {res[label]}")
     return res
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="slater_128")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="nanoparticle_512")
+    ap.add_argument("--precision", default="fp64", choices=["fp32", "fp64"],
+                    help="arithmetic of the headline value (the other form is reported beside it)")
+    ap.add_argument("--no-second-form", action="store_true", help="time only the headline precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workload", default="slater_128",
+                    help="workload of the oracle timing (the 512^3 workload is beyond a bounded host run)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=40.0)
@@ -136,37 +232,25 @@ def main() -> int:
     dev = torch.device("cuda:0")
     kt = inputs.synthetic_kernel_table()
     w = inputs.workload(args.workload)
-    print(f"[bench] workload {args.workload} grid {w.grid} precision {args.precision}", file=sys.stderr, flush=True)
+    say(f"workload {args.workload} grid {w.grid}, headline precision {args.precision}")
     t_in = time.perf_counter()
-    n, g = w.density(device="cuda", progress=lambda done, total: print(
-        f"[bench] density: {done}/{total} blobs", file=sys.stderr, flush=True))
+    n, g = w.density(device="cuda", progress=lambda done, total: say(f"density: {done}/{total} blobs"))
     torch.cuda.synchronize()
-    print(f"[bench] density ready in {time.perf_counter() - t_in:.1f} s", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    f = vdwxc.Functional(w.grid, w.cell, flavour="DF1", precision=args.precision, table=kt)
-    v = torch.empty_like(n)
-    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    say(f"density ready in {time.perf_counter() - t_in:.1f} s")
 
-    for _ in range(args.warmup):
-        f.potential_async(n, g, v, e)
-    torch.cuda.synchronize()
-    # timed region 1: throughput, no instrumentation
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        f.potential_async(n, g, v, e)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # timed region 2: the same steps with the library's per-kernel HIP events (recorded on the
-    # stream the kernels run on), for the per-kernel durations behind the roofline figure
-    f.enable_timing(True)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        f.potential_async(n, g, v, e)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    stages = f.read_timing()
-    f.enable_timing(False)
+    forms = [args.precision] + ([] if args.no_second_form else [p for p in ("fp64", "fp32") if p != args.precision])
+    results = {}
+    for prec in forms:
+        f = vdwxc.Functional(w.grid, w.cell, flavour="DF1", precision=prec, table=kt)
+        ms, stages, roof, v, E = time_form(f, n, g, args.steps, args.warmup, w.grid, prec)
+        roof["traffic"] = profiled_traffic(args.workload, prec, roof["kernel"])
+        f.close()
+        results[prec] = dict(ms=ms, stages=stages, roofline=roof, v=v, E=E)
+        say(f"{prec}: {ms:.3f} ms/step, {w.npoints / ms * 1e3:.4e} pts/s, E = {E:.12e}, "
+            f"dominant {roof['kernel']} {roof['frac']:.3f} of HBM")
+        if prec == args.precision:
+            torch.cuda.synchronize()
+        del f
     if args.copy_calibration_mb:
         # one streaming elementwise kernel (negation) reading and writing N bytes each
         nel = args.copy_calibration_mb * (1 << 20) // 8
@@ -176,70 +260,68 @@ def main() -> int:
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    elapsed = t1 - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    ms_per_step_instrumented = 1e3 * (t3 - t2) / args.steps
-    value = w.npoints * args.steps / elapsed
-    E_gpu = float(e.item())
-    print(f"[bench] {ms_per_step:.3f} ms/step, {value:.4e} pts/s, E = {E_gpu:.12e}", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel
-    per_stage = {k: {"ms_avg": ms / cnt, "launches": cnt,
-                     "GBps": stage_bytes(k, w.grid, args.precision) / (ms / cnt * 1e-3) / 1e9}
-                 for k, (ms, cnt) in stages.items()}
-    dom = max(stages, key=lambda k: stages[k][0])
-    avg_s = stages[dom][0] / stages[dom][1] * 1e-3
-    achieved = stage_bytes(dom, w.grid, args.precision) / avg_s / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": profiled_traffic(args.workload, args.precision, dom),
-                "algorithmic_bytes_per_launch": stage_bytes(dom, w.grid, args.precision),
-                "avg_launch_ms": round(avg_s * 1e3, 4),
-                "timing": "HIP events around each kernel over a second timed region of the same steps "
-                          f"({ms_per_step_instrumented:.4f} ms/step with the events)"}
+    head = results[args.precision]
+    second = None
+    if len(forms) > 1:
+        other = forms[1]
+        r = results[other]
+        ref64 = results["fp64"]
+        r32 = results["fp32"]
+        d = torch.abs(r32["v"] - ref64["v"])
+        vmax = float(torch.max(torch.abs(ref64["v"])))
+        core = n >= 1e-6
+        second = {"precision": "fp32_mixed" if other == "fp32" else "fp64",
+                  "value": w.npoints / r["ms"] * 1e3, "unit": "grid pts/s", "ms_per_step": r["ms"],
+                  "roofline": r["roofline"], "stages": r["stages"],
+                  "fp32_vs_fp64": {"E_rel": abs(r32["E"] - ref64["E"]) / abs(ref64["E"]),
+                                   "v_maxnorm_rel_n_ge_1e-6": float(torch.max(torch.where(core, d, torch.zeros_like(d)))) / vmax,
+                                   "v_maxnorm_rel_all": float(torch.max(d)) / vmax,
+                                   "v_density_weighted_l1": float(torch.sum(n * d) / torch.sum(n * torch.abs(ref64["v"])))}}
+    for r in results.values():
+        r["v"] = None
+    torch.cuda.empty_cache()
 
     cpu = None
     accuracy = None
     if not args.no_cpu_baseline:
-        bw = w if w.npoints <= 128 ** 3 else inputs.workload("slater_128")
-        bname = args.workload if bw is w else "slater_128"
-        if bw is w:
-            nc, gc = n.cpu().numpy(), g.cpu().numpy()
-        else:
-            bn, bg = bw.density(device="cuda")
-            nc, gc = bn.cpu().numpy(), bg.cpu().numpy()
-        print(f"[bench] oracle CPU baseline on {bname}", file=sys.stderr, flush=True)
-        cpu, E_ref, v_ref = cpu_baseline(bname, nc, gc, bw, kt)
-        if bw is w:
-            vv = v.cpu().numpy()
-            accuracy = {"E_rel_err_vs_oracle": abs(E_gpu - E_ref) / abs(E_ref),
-                        "v_maxnorm_rel_err_vs_oracle": float(np.max(np.abs(vv - v_ref)) / np.max(np.abs(v_ref))),
-                        "v_density_weighted_l1": float(np.sum(nc * np.abs(vv - v_ref)) / np.sum(nc * np.abs(v_ref)))}
+        bw = inputs.workload(args.cpu_workload)
+        bn, bg = bw.density(device="cuda")
+        nc, gc = bn.cpu().numpy(), bg.cpu().numpy()
+        say(f"oracle CPU baseline on {args.cpu_workload}")
+        cpu = cpu_baseline(args.cpu_workload, nc, gc, bw, kt)
+        say(f"oracle: {cpu['seconds']} s, stages {cpu['stage_seconds']}")
+        del bn, bg
 
     serve = None
     if not args.no_serve:
-        serve = serving_measurement(kt, args.serve_requests, args.serve_rate, args.precision)
+        serve = serving_measurement(kt, args.serve_requests, args.serve_rate, "fp32")
 
+    prec = args.precision
     out = {
-        "metric": "grid pts/s for E_c^nl+v_c^nl (Nalpha=20) at stated rel. error; p50/p99 serve latency",
-        "value": value,
+        "metric": METRIC,
+        "value": w.npoints / head["ms"] * 1e3,
         "unit": "grid pts/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f32" if prec == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": list(w.grid), "cell_bohr": float(w.cell[0, 0]),
-                   "n_alpha": M, "precision": "fp32_mixed (fp64 q0/splines/sums)" if args.precision == "fp32" else "fp64",
+                   "n_alpha": M,
+                   "precision": ("fp32_mixed (q0 and its derivatives, energy and derivative sums, spectral "
+                                 "gradient in fp64; theta, FFTs, table, contraction in fp32)")
+                   if prec == "fp32" else "fp64 throughout",
                    "entry": "vdwxc_calculate_potential_async, analytic gradient", "parallelism": "1 GPU"},
-        "roofline": roofline,
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "accuracy": accuracy,
-        "stages": {k: {kk: round(vv, 4) for kk, vv in d.items()} for k, d in per_stage.items()},
+        "stages": head["stages"],
+        "fp32_mixed" if prec == "fp64" else "fp64": second,
         "serving": serve,
     }
     print(json.dumps(out), flush=True)

@@ -50,24 +50,35 @@ typedef enum {
 /* Functional flavour: the gradient coefficient Z_ab of q0 (paper appendix). */
 typedef enum { VDWXC_DF1 = 1 /* Z_ab = -0.8491 */, VDWXC_DF2 = 2 /* Z_ab = -1.887 */ } vdwxc_flavour;
 
-/* Arithmetic of the FFTs and the contraction.  FP64: everything in double precision (the
- * paper's choice, Sec. 6).  FP32_MIXED: q0, splines and the spectral gradient in FP64, theta,
- * FFTs, the kernel table and the contraction in FP32, energy and derivative sums in FP64. */
+/* Arithmetic of the path.  FP64: everything in double precision (the paper's choice, Sec. 6).
+ * FP32_MIXED: in FP64 - q0 with its saturation and its two partial derivatives (every point, the
+ * vacuum tail included), the spectral gradient of n, the per-k energy accumulation and the final
+ * energy sum, and the sums of the derivative assembly over the fields; in FP32 - the spline state
+ * handed from q0 to theta and to the assembly (interval position t, n dq0/dn, n dq0/dsigma), the
+ * cubic spline weights and theta_a = n p_a(q0), every FFT, the kernel table, its interpolation and
+ * the contraction, and the products F_a * (spline factor) before they enter the FP64 sums. */
 typedef enum { VDWXC_FP64 = 0, VDWXC_FP32_MIXED = 1 } vdwxc_precision;
 
 /* Create a handle for one grid and cell (paper Sec. 6, steps 1-3: vdwxc_new, set_unit_cell,
  * init).  grid[3] = {N1, N2, N3}; cell[9] as above.  The kernel table is read from
  * kernel_table_path, a binary file: bytes "VDWK", uint32 version (=1), uint32 M (q-mesh points,
- * 4 <= M <= 20), uint32 nk (>= 2), float64 kmax, float64 qmesh[M] (strictly increasing, > 0),
- * float64 table[nk][M][M] with table[j][a][b] = phi_ab(j*kmax/(nk-1)) (symmetric in a, b), all
- * little endian.  The grid's largest |G| must be below kmax (else VDWXC_EINVAL).  hip_stream is
- * the stream later calls enqueue on.  On success *out receives the handle; it owns device memory
- * of vdwxc_workspace_bytes() plus the tables, until vdwxc_finalize. */
+ * 4 <= M <= 20), uint32 nk (>= 2), float64 kmax, float64 qmesh[M] (strictly increasing, > 0, the
+ * last point >= 5, the saturation value of q0 in the paper's appendix), float64 table[nk][M][M]
+ * with table[j][a][b] = phi_ab(j*kmax/(nk-1)) (symmetric in a, b), all little endian; nk is
+ * limited so that the reordered table stays below 2 GiB (about 639 000 nodes), else VDWXC_ETABLE.
+ * kernel_table_path NULL means the default table: the file named by the environment variable
+ * VDWXC_KERNEL_TABLE, else vdw_kernel_table.vdwk in the directory of this library (written by
+ * the build).  The grid's largest |G| must be below kmax (else VDWXC_EINVAL).  hip_stream is the
+ * stream later calls enqueue on.  On success *out receives the handle; it owns device memory of
+ * vdwxc_workspace_bytes_m() for its work buffers until vdwxc_finalize.  The read-only tables (the
+ * q-mesh with its spline moments, the kernel table in the handle's precision, the twiddles of each
+ * axis length) are shared by all handles on the device that use the same table and lengths,
+ * reference counted, and freed with the last of them. */
 vdwxc_status vdwxc_init(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
                         vdwxc_precision precision, const char* kernel_table_path, void* hip_stream);
 
-/* As vdwxc_init, with the kernel table given as HOST arrays (copied; the caller keeps
- * ownership): qmesh[nq], table[nk][nq][nq] as in the file format. */
+/* As vdwxc_init, with the kernel table given as HOST arrays (read during the call; the caller
+ * keeps ownership): qmesh[nq], table[nk][nq][nq] as in the file format, the same limits. */
 vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
                               vdwxc_precision precision, int nq, const double* qmesh, int nk, double kmax,
                               const double* table, void* hip_stream);
@@ -100,9 +111,13 @@ vdwxc_status vdwxc_calculate_potential_async(vdwxc_handle h, const double* n, co
 vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double* sigma, double* dedn,
                                    double* dedsigma, double* energy_dev);
 
-/* Device memory a handle for this grid allocates for its work buffers (excluding the kernel
- * table and plans), for admission control; 0 if the grid is invalid.  Host-only. */
-size_t vdwxc_workspace_bytes(const int grid[3], vdwxc_precision precision, int nq);
+/* Device memory a handle for this grid allocates for its work buffers (excluding the shared
+ * tables), for admission control, with the paper's N_alpha = 20 q-mesh points; 0 if the grid or
+ * precision is invalid.  Host-only. */
+size_t vdwxc_workspace_bytes(const int grid[3], vdwxc_precision precision);
+
+/* As vdwxc_workspace_bytes for a q-mesh of nq points (4 <= nq <= 20). */
+size_t vdwxc_workspace_bytes_m(const int grid[3], vdwxc_precision precision, int nq);
 
 /* Change the stream later calls enqueue on. */
 vdwxc_status vdwxc_set_stream(vdwxc_handle h, void* hip_stream);

@@ -1,4 +1,5 @@
-"""Build of the HIP library libvdwxc_gpu.so (gfx950) in-tree, with hipcc.
+"""Build of the HIP library libvdwxc_gpu.so (gfx950) in-tree, with hipcc, and of the default
+kernel-table file beside it.
 
     python -m paper_1703_06999_amd.build
 """
@@ -43,7 +44,21 @@ def build(verbose: bool = True) -> str:
     if verbose and out.strip():
         print(out)
     os.replace(tmp, LIB)
+    write_default_table()
     return LIB
+
+
+DEFAULT_TABLE = os.path.join(LIB_DIR, "vdw_kernel_table.vdwk")
+
+
+def write_default_table() -> str:
+    """The table file the library reads when vdwxc_init gets a NULL path: the package's synthetic
+    kernel table (inputs.synthetic_kernel_table), next to the library."""
+    sys.path.insert(0, ROOT)
+    from paper_1703_06999_amd import inputs
+    inputs.synthetic_kernel_table().save(DEFAULT_TABLE + ".tmp")
+    os.replace(DEFAULT_TABLE + ".tmp", DEFAULT_TABLE)
+    return DEFAULT_TABLE
 
 
 if __name__ == "__main__":

@@ -499,16 +499,18 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 // per two pairs and one FMA per interpolation.  Every lane reads its own nodes; kx and -kx, which
 // have the same |G| in orthogonal cells, sit in adjacent lanes and share them.
 
-// pair index of (a <= b) for a table dimensioned by kMaxQ, and its inverse
-__host__ __device__ constexpr int pair_index(int a, int b) { return a * kMaxQ - a * (a - 1) / 2 + (b - a); }
+// Index of the unordered pair (a <= b), ordered by the larger index b: (0,0), (0,1), (1,1), (0,2),
+// ...  The pairs of a q-mesh of M points are then exactly the first M(M+1)/2, so a shorter mesh
+// reads and contracts only those.  kPairs lists (row a, col b) in this order.
+__host__ __device__ constexpr int pair_index(int a, int b) { return b * (b + 1) / 2 + a; }
 constexpr int kNumPairs = kMaxQ * (kMaxQ + 1) / 2;
 static_assert(kNumPairs % 2 == 0, "pairs are stored two per table entry");
 struct PairList {
   int row[kNumPairs], col[kNumPairs];
   constexpr PairList() : row(), col() {
     int p = 0;
-    for (int a = 0; a < kMaxQ; ++a)
-      for (int b = a; b < kMaxQ; ++b) {
+    for (int b = 0; b < kMaxQ; ++b)
+      for (int a = 0; a <= b; ++a) {
         row[p] = a;
         col[p] = b;
         ++p;
@@ -516,6 +518,11 @@ struct PairList {
   }
 };
 constexpr PairList kPairs{};
+
+// load chunks of the contraction that hold a pair of an M-point q-mesh
+__host__ __device__ constexpr int used_chunks(int M, int chunk) {
+  return ((M * (M + 1) / 2 + 1) / 2 + chunk - 1) / chunk;
+}
 
 #ifndef VDWXC_XCHUNK
 #define VDWXC_XCHUNK 3
@@ -637,11 +644,14 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
       if ((cc) * kXChunk + i < kGroups) buffer_load_quad(trs, joff + i * kQ, tcur, (dst)[i]);     \
     tcur += cstride;                                                                              \
   } while (0)
+    // chunks past the pairs of the q-mesh hold zeros: stop before them (M < 20)
+    const int nchunks = used_chunks(M, kXChunk);
     Quad<T> buf[2][kXChunk];
     VDWXC_TLOAD_CHUNK(buf[0], 0);
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-      if (c + 1 < kChunks) VDWXC_TLOAD_CHUNK(buf[(c + 1) & 1], c + 1);
+      if (c >= nchunks) break;
+      if (c + 1 < kChunks && c + 1 < nchunks) VDWXC_TLOAD_CHUNK(buf[(c + 1) & 1], c + 1);
 #pragma unroll
       for (int i = 0; i < kXChunk; ++i) {
         const int grp = c * kXChunk + i;
@@ -758,6 +768,12 @@ struct PairPrefetch {
     }
   }
 };
+
+// Clear an evaluation's NaN flags (a fill kernel rather than a memset, so that it can sit in a
+// captured graph).  One block.
+__global__ void k_clear_flags(int* __restrict__ flag) {
+  if (threadIdx.x < 2) flag[threadIdx.x] = 0;
+}
 
 // ---- energy: fixed-order sum of the per-column partials (one block) ----------------------------
 // Eight independent loads in flight per thread, then a fixed reduction tree: the same inputs give

@@ -1,10 +1,12 @@
 // Host runtime and C ABI of the vdW-DF nonlocal-correlation library (see include/vdwxc_gpu.h).
 //
-// A handle holds: the grid and cell, per-axis FFT plans and twiddle tables, the q-mesh with the
-// second-derivative matrix of its natural helper splines, the kernel table (FP64 or FP32), two
-// complex work buffers A and B, the dE/dsigma and gradient buffers of the potential entry, the
-// per-column energy partials and a NaN flag.  A calculate call only enqueues kernels on the
-// handle's stream; the synchronous entry points then copy back one small result.
+// A handle holds: the grid and cell, per-axis FFT plans, references to the shared read-only tables
+// (the q-mesh with the second-derivative matrix of its natural helper splines, the kernel table in
+// FP64 or FP32, the twiddle tables of its axis lengths) and one block of work memory: two complex
+// work buffers A and B, the dE/dsigma and gradient buffers of the potential entry, the per-point
+// spline state, the per-column energy partials and a NaN flag.  A calculate call only enqueues
+// kernels on the handle's stream; the synchronous entry points then copy back one small result.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,6 +62,90 @@ struct Launch {
   int sets = 1;   // assembly: line sets (field pairs per transform)
 };
 
+// Device buffers of one evaluation.  A handle owns one set; the allocation-free entry point
+// carves one out of the static scratch array.  `timed`: record the per-stage HIP events (never on
+// the allocation-free path, where taking an event could allocate).
+struct Work {
+  void* A = nullptr;           // complex [f][kz][x][y] (z pass output), real fields of the div/grad passes
+  void* B = nullptr;           // complex [f][ky][kz][x] (y pass output)
+  double* S = nullptr;         // dE/dsigma of the potential entry [N]
+  void* state = nullptr;       // per-point spline state Quad<T> [N], theta pass -> assembly
+  double* G = nullptr;         // spectral gradient [3][N]
+  double* partials = nullptr;  // per-column energy partials [N2 * H3]
+  int* flag = nullptr;         // [0]: NaN seen by the theta pass, [1]: the last evaluation's flag
+  bool timed = true;
+};
+
+// byte offsets of the buffers of Work in one block (each 256-byte aligned) and its size
+struct Layout {
+  size_t A, B, S, state, G, partials, flag, total;
+};
+
+// bytes per grid point of the spline state passed from the theta pass to the assembly
+size_t state_bytes(vdwxc_precision p) { return p == VDWXC_FP64 ? sizeof(Quad<double>) : sizeof(Quad<float>); }
+
+size_t complex_buffer_bytes(int n1, int n2, int n3, vdwxc_precision p, int M) {
+  const size_t nk = size_t(n1) * n2 * (n3 / 2 + 1);
+  const size_t fields = (p == VDWXC_FP64) ? std::max(M, 3) * 16 : std::max<size_t>(M * 8, 3 * 16);
+  return nk * fields;
+}
+
+Layout workspace_layout(int n1, int n2, int n3, vdwxc_precision p, int M) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t N = size_t(n1) * n2 * n3, cplx = complex_buffer_bytes(n1, n2, n3, p, M);
+  Layout L{};
+  size_t o = 0;
+  L.A = o; o += al(cplx);
+  L.B = o; o += al(cplx);
+  L.S = o; o += al(N * sizeof(double));
+  L.state = o; o += al(N * state_bytes(p));
+  L.G = o; o += al(3 * N * sizeof(double));
+  L.partials = o; o += al(size_t(n2) * (n3 / 2 + 1) * sizeof(double));
+  L.flag = o; o += al(2 * sizeof(int));
+  L.total = o;
+  return L;
+}
+
+Work carve(void* base, const Layout& L) {
+  unsigned char* b = static_cast<unsigned char*>(base);
+  Work w;
+  w.A = b + L.A;
+  w.B = b + L.B;
+  w.S = reinterpret_cast<double*>(b + L.S);
+  w.state = b + L.state;
+  w.G = reinterpret_cast<double*>(b + L.G);
+  w.partials = reinterpret_cast<double*>(b + L.partials);
+  w.flag = reinterpret_cast<int*>(b + L.flag);
+  return w;
+}
+
+// ---- read-only tables shared between handles --------------------------------------------------
+// Handles on one device that use the same kernel table (q-mesh, k-grid and values, compared in
+// full) in the same precision share one device copy of it, together with the q-mesh and the
+// spline moments; handles whose grids share an axis length share its twiddle tables.  Entries are
+// reference counted and freed with their last handle.
+struct TableEntry {
+  int device = 0;
+  vdwxc_precision precision = VDWXC_FP64;
+  int nq = 0, nk = 0;
+  double kmax = 0.0;
+  std::vector<double> qmesh, table;   // host copies of the inputs: the key
+  double* d_q = nullptr;
+  double* d_mm = nullptr;
+  Quad<double>* d_table64 = nullptr;  // chunk-major pair table, see build_pair_table
+  Quad<float>* d_table32 = nullptr;
+  int refs = 0;
+};
+struct TwiddleEntry {
+  int device = 0, n = 0;
+  double2* d64 = nullptr;   // exp(-2 pi i t / n), t < n
+  float2* d32 = nullptr;
+  int refs = 0;
+};
+std::mutex g_cache_mutex;
+std::vector<TableEntry*> g_tables;
+std::vector<TwiddleEntry*> g_twiddles;
+
 }  // namespace
 
 struct vdwxc_ctx {
@@ -80,22 +167,15 @@ struct vdwxc_ctx {
   size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
   bool x_capped = false;   // launch the register-capped contraction kernel
   bool ortho = false;
-  // device memory
-  double* d_q = nullptr;
-  double* d_mm = nullptr;
-  Quad<double>* d_table64 = nullptr;   // [pair / 2][j]: T_j of pairs 2g, 2g+1, then T_j+1 - T_j
-  Quad<float>* d_table32 = nullptr;
-  double2* d_tw64[3] = {nullptr, nullptr, nullptr};
-  float2* d_tw32[3] = {nullptr, nullptr, nullptr};
-  void* d_A = nullptr;
-  void* d_B = nullptr;
-  size_t buf_bytes = 0;
-  double* d_S = nullptr;       // dE/dsigma of the potential entry
-  void* d_state = nullptr;     // per-point spline state, Quad<T> [N], theta pass -> assembly
-  double* d_G = nullptr;       // spectral gradient [3][N]
-  double* d_partials = nullptr;
+  // shared read-only device tables (reference counted, see TableEntry / TwiddleEntry)
+  TableEntry* tab = nullptr;
+  TwiddleEntry* tw[3] = {nullptr, nullptr, nullptr};
+  // the handle's own work memory: one allocation of `ws_bytes`, carved by workspace_layout
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t buf_bytes = 0;        // each complex work buffer
+  Work work;
   double* d_energy = nullptr;  // energy of the synchronous entries
-  int* d_flag = nullptr;
   double* h_energy = nullptr;  // pinned
   int* h_flag = nullptr;       // pinned
   std::string last_error;
@@ -362,15 +442,6 @@ bool pick_div(K* kernel, bool zpass, bool p_half, int n, int first_tile, Launch&
   return pick_occupancy(kernel, c, nc, out, lds);
 }
 
-// bytes per grid point of the spline state passed from the theta pass to the assembly
-size_t state_bytes(vdwxc_precision p) { return p == VDWXC_FP64 ? sizeof(Quad<double>) : sizeof(Quad<float>); }
-
-size_t complex_buffer_bytes(int n1, int n2, int n3, vdwxc_precision p, int M) {
-  const size_t nk = size_t(n1) * n2 * (n3 / 2 + 1);
-  const size_t fields = (p == VDWXC_FP64) ? std::max(M, 3) * 16 : std::max<size_t>(M * 8, 3 * 16);
-  return nk * fields;
-}
-
 template <typename F>
 void set_lds_limit(F* kernel, size_t bytes) {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -387,25 +458,180 @@ vdwxc_status validate_common(const int grid[3], const double cell[9]) {
   return VDWXC_OK;
 }
 
-void release(vdwxc_ctx* h) {
-  if (!h) return;
-  for (auto& p : h->pending) { (void)hipEventDestroy(p.start); (void)hipEventDestroy(p.stop); }
-  for (auto e : h->free_events) (void)hipEventDestroy(e);
-  auto f = [](void* p) { if (p) (void)hipFree(p); };
-  f(h->d_q); f(h->d_mm); f(h->d_table64); f(h->d_table32);
-  for (int i = 0; i < 3; ++i) { f(h->d_tw64[i]); f(h->d_tw32[i]); }
-  f(h->d_A); f(h->d_B); f(h->d_S); f(h->d_state); f(h->d_G); f(h->d_partials); f(h->d_energy); f(h->d_flag);
-  if (h->h_energy) (void)hipHostFree(h->h_energy);
-  if (h->h_flag) (void)hipHostFree(h->h_flag);
-  delete h;
-}
-
 template <typename T>
 hipError_t upload(T** dst, const T* src, size_t count) {
   hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T));
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
 }
+
+void free_table(TableEntry* t) {
+  auto f = [](void* p) { if (p) (void)hipFree(p); };
+  f(t->d_q); f(t->d_mm); f(t->d_table64); f(t->d_table32);
+  delete t;
+}
+
+void free_twiddles(TwiddleEntry* t) {
+  if (t->d64) (void)hipFree(t->d64);
+  if (t->d32) (void)hipFree(t->d32);
+  delete t;
+}
+
+// drop one reference (device `dev` current); the entry is freed with its last handle
+void release_table(TableEntry* t) {
+  if (!t) return;
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  if (--t->refs > 0) return;
+  g_tables.erase(std::remove(g_tables.begin(), g_tables.end(), t), g_tables.end());
+  free_table(t);
+}
+
+void release_twiddles(TwiddleEntry* t) {
+  if (!t) return;
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  if (--t->refs > 0) return;
+  g_twiddles.erase(std::remove(g_twiddles.begin(), g_twiddles.end(), t), g_twiddles.end());
+  free_twiddles(t);
+}
+
+void release(vdwxc_ctx* h) {
+  if (!h) return;
+  for (auto& p : h->pending) { (void)hipEventDestroy(p.start); (void)hipEventDestroy(p.stop); }
+  for (auto e : h->free_events) (void)hipEventDestroy(e);
+  release_table(h->tab);
+  for (int i = 0; i < 3; ++i) release_twiddles(h->tw[i]);
+  if (h->d_ws) (void)hipFree(h->d_ws);
+  if (h->d_energy) (void)hipFree(h->d_energy);
+  if (h->h_energy) (void)hipHostFree(h->h_energy);
+  if (h->h_flag) (void)hipHostFree(h->h_flag);
+  delete h;
+}
+
+// Device bytes of the contraction's pair table: per group of two unordered pairs and node j one
+// Quad (T_j of both pairs, then T_j+1 - T_j of both), padded to whole chunks of kXChunk groups.
+size_t pair_table_bytes(vdwxc_precision p, int nk) {
+  constexpr int kGroups = kNumPairs / 2, kChunks = (kGroups + kXChunk - 1) / kXChunk;
+  return size_t(kChunks) * kXChunk * size_t(nk) * (p == VDWXC_FP64 ? sizeof(Quad<double>) : sizeof(Quad<float>));
+}
+
+// The kernel table reordered for the contraction: per unordered pair p = (a <= b) (pair_index
+// order, so the pairs of a q-mesh of M points are the first M(M+1)/2) and node j, T_j and
+// T_j+1 - T_j (0 at the last node).  Pairs 2g and 2g+1 share entry (g, j) = (T_j(2g), T_j(2g+1),
+// D_j(2g), D_j(2g+1)), stored chunk-major at [g / kXChunk][j][g % kXChunk] (the contraction reads
+// a chunk's entries of one node together).  Pairs with a or b >= nq stay zero.
+std::vector<Quad<double>> build_pair_table(int nq, int nk, const double* table) {
+  constexpr int kGroups = kNumPairs / 2, kChunks = (kGroups + kXChunk - 1) / kXChunk;
+  const size_t tn = size_t(kChunks) * kXChunk * nk;
+  std::vector<Quad<double>> t64(tn, Quad<double>{0.0, 0.0, 0.0, 0.0});
+  for (int a = 0; a < nq; ++a)
+    for (int b = a; b < nq; ++b) {
+      const int pr = pair_index(a, b);
+      for (int j = 0; j < nk; ++j) {
+        const double tj = table[(size_t(j) * nq + a) * nq + b];
+        const double dj = j + 1 < nk ? table[(size_t(j + 1) * nq + a) * nq + b] - tj : 0.0;
+        const int grp = pr / 2;
+        Quad<double>& q = t64[(size_t(grp / kXChunk) * nk + j) * kXChunk + grp % kXChunk];
+        if (pr % 2 == 0) {
+          q.x = tj;
+          q.z = dj;
+        } else {
+          q.y = tj;
+          q.w = dj;
+        }
+      }
+    }
+  return t64;
+}
+
+// the shared device copy of a kernel table for `device` (current) and precision, created on first
+// use; the caller holds one reference
+hipError_t acquire_table(int device, vdwxc_precision precision, int nq, const double* qmesh, int nk, double kmax,
+                         const double* table, TableEntry** out) {
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  const size_t tsz = size_t(nk) * nq * nq;
+  for (TableEntry* t : g_tables) {
+    if (t->device == device && t->precision == precision && t->nq == nq && t->nk == nk && t->kmax == kmax &&
+        std::memcmp(t->qmesh.data(), qmesh, nq * sizeof(double)) == 0 &&
+        std::memcmp(t->table.data(), table, tsz * sizeof(double)) == 0) {
+      ++t->refs;
+      *out = t;
+      return hipSuccess;
+    }
+  }
+  TableEntry* t = new (std::nothrow) TableEntry();
+  if (!t) return hipErrorOutOfMemory;
+  t->device = device;
+  t->precision = precision;
+  t->nq = nq;
+  t->nk = nk;
+  t->kmax = kmax;
+  t->qmesh.assign(qmesh, qmesh + nq);
+  t->table.assign(table, table + tsz);
+  std::vector<double> mm;
+  natural_spline_moments(t->qmesh, mm);
+  hipError_t e = upload(&t->d_q, qmesh, nq);
+  if (e == hipSuccess) e = upload(&t->d_mm, mm.data(), mm.size());
+  if (e == hipSuccess) {
+    const std::vector<Quad<double>> t64 = build_pair_table(nq, nk, table);
+    if (precision == VDWXC_FP64) {
+      e = upload(&t->d_table64, t64.data(), t64.size());
+    } else {
+      std::vector<Quad<float>> t32(t64.size());
+      for (size_t i = 0; i < t64.size(); ++i)
+        t32[i] = Quad<float>{float(t64[i].x), float(t64[i].y), float(t64[i].z), float(t64[i].w)};
+      e = upload(&t->d_table32, t32.data(), t32.size());
+    }
+  }
+  if (e != hipSuccess) {
+    free_table(t);
+    return e;
+  }
+  t->refs = 1;
+  g_tables.push_back(t);
+  *out = t;
+  return hipSuccess;
+}
+
+// the shared twiddle tables (both precisions) of an axis of length n on `device` (current)
+hipError_t acquire_twiddles(int device, int n, TwiddleEntry** out) {
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  for (TwiddleEntry* t : g_twiddles)
+    if (t->device == device && t->n == n) {
+      ++t->refs;
+      *out = t;
+      return hipSuccess;
+    }
+  TwiddleEntry* t = new (std::nothrow) TwiddleEntry();
+  if (!t) return hipErrorOutOfMemory;
+  t->device = device;
+  t->n = n;
+  const auto t64 = twiddles<double2, double>(n);
+  const auto t32 = twiddles<float2, float>(n);
+  hipError_t e = upload(&t->d64, t64.data(), t64.size());
+  if (e == hipSuccess) e = upload(&t->d32, t32.data(), t32.size());
+  if (e != hipSuccess) {
+    free_twiddles(t);
+    return e;
+  }
+  t->refs = 1;
+  g_twiddles.push_back(t);
+  *out = t;
+  return hipSuccess;
+}
+
+// NULL kernel-table path: $VDWXC_KERNEL_TABLE, else vdw_kernel_table.vdwk next to this library
+std::string default_table_path() {
+  if (const char* e = std::getenv("VDWXC_KERNEL_TABLE"))
+    if (*e) return std::string(e);
+  Dl_info info;
+  if (dladdr(reinterpret_cast<void*>(&default_table_path), &info) && info.dli_fname) {
+    const std::string p(info.dli_fname);
+    const size_t k = p.rfind('/');
+    return (k == std::string::npos ? std::string(".") : p.substr(0, k)) + "/vdw_kernel_table.vdwk";
+  }
+  return "vdw_kernel_table.vdwk";
+}
+
 
 }  // namespace
 
@@ -422,8 +648,8 @@ template <> struct Prec<double> {
   static const Launch& y(const vdwxc_ctx* h) { return h->yl64; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz64 : a == 1 ? h->dy64 : h->dx64; }
-  static const double2* tw(const vdwxc_ctx* h, int a) { return h->d_tw64[a]; }
-  static const Quad<double>* table(const vdwxc_ctx* h) { return h->d_table64; }
+  static const double2* tw(const vdwxc_ctx* h, int a) { return h->tw[a]->d64; }
+  static const Quad<double>* table(const vdwxc_ctx* h) { return h->tab->d_table64; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta64; }
   static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm64; }
 };
@@ -433,8 +659,8 @@ template <> struct Prec<float> {
   static const Launch& y(const vdwxc_ctx* h) { return h->yl32; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz32 : a == 1 ? h->dy32 : h->dx32; }
-  static const float2* tw(const vdwxc_ctx* h, int a) { return h->d_tw32[a]; }
-  static const Quad<float>* table(const vdwxc_ctx* h) { return h->d_table32; }
+  static const float2* tw(const vdwxc_ctx* h, int a) { return h->tw[a]->d32; }
+  static const Quad<float>* table(const vdwxc_ctx* h) { return h->tab->d_table32; }
   static size_t theta_lds(const vdwxc_ctx* h) { return h->lds_theta32; }
   static size_t asm_lds(const vdwxc_ctx* h) { return h->lds_asm32; }
 };
@@ -450,14 +676,14 @@ hipEvent_t take_event(vdwxc_ctx* h) {
   return e;
 }
 
-void stage_begin(vdwxc_ctx* h) {
-  if (!h->timing) return;
+void stage_begin(vdwxc_ctx* h, const Work& w) {
+  if (!h->timing || !w.timed) return;
   h->cur_start = take_event(h);
   if (h->cur_start) (void)hipEventRecord(h->cur_start, h->stream);
 }
 
-void stage_end(vdwxc_ctx* h, int stage) {
-  if (!h->timing || !h->cur_start) return;
+void stage_end(vdwxc_ctx* h, const Work& w, int stage) {
+  if (!h->timing || !w.timed || !h->cur_start) return;
   hipEvent_t stop = take_event(h);
   if (!stop) return;
   (void)hipEventRecord(stop, h->stream);
@@ -466,109 +692,110 @@ void stage_end(vdwxc_ctx* h, int stage) {
 }
 
 template <typename T>
-void enqueue_ypass(vdwxc_ctx* h, int nf, int dir, int stage) {
+void enqueue_ypass(vdwxc_ctx* h, const Work& w, int nf, int dir, int stage) {
   using T2 = typename Cx<T>::type;
   const Launch& L = Prec<T>::y(h);
   dim3 grid((h->n1 + L.tile - 1) / L.tile, h->h3, nf);
-  T2* A = static_cast<T2*>(h->d_A);
-  T2* B = static_cast<T2*>(h->d_B);
-  stage_begin(h);
+  T2* A = static_cast<T2*>(w.A);
+  T2* B = static_cast<T2*>(w.B);
+  stage_begin(h, w);
   if (dir < 0)
     hipLaunchKernelGGL((k_ypass<T, kEPT, -1>), grid, dim3(L.nthr), L.lds, h->stream, A, B, Prec<T>::tw(h, 1),
                        h->geo, h->plan[1], L.tile, L.lstride);
   else
     hipLaunchKernelGGL((k_ypass<T, kEPT, +1>), grid, dim3(L.nthr), L.lds, h->stream, B, A, Prec<T>::tw(h, 1),
                        h->geo, h->plan[1], L.tile, L.lstride);
-  stage_end(h, stage);
+  stage_end(h, w, stage);
 }
 
 // spectral gradient of the FP64 density n into out ([3][N], FP64), one axis at a time
 // (k_grad_z, k_grad_y, k_grad_x); the intermediate real fields sit in the work buffers ([2][N] in
 // A, [3][N] in B), in FP64 whatever the handle's precision, because the gradient feeds q0
-void enqueue_gradient(vdwxc_ctx* h, const double* src, double* out) {
-  double* F2 = static_cast<double*>(h->d_A);
-  double* F3 = static_cast<double*>(h->d_B);
-  stage_begin(h);
+void enqueue_gradient(vdwxc_ctx* h, const Work& w, const double* src, double* out) {
+  double* F2 = static_cast<double*>(w.A);
+  double* F3 = static_cast<double*>(w.B);
+  stage_begin(h, w);
   hipLaunchKernelGGL((k_grad_z<double, kEPT>), dim3((h->n2 + h->gz.tile - 1) / h->gz.tile, h->n1), dim3(h->gz.nthr),
-                     h->gz.lds, h->stream, src, F2, h->d_tw64[2], h->geo, h->plan[2], h->gz.tile, h->gz.lstride);
-  stage_end(h, VDWXC_STAGE_GRAD_Z);
-  stage_begin(h);
+                     h->gz.lds, h->stream, src, F2, h->tw[2]->d64, h->geo, h->plan[2], h->gz.tile, h->gz.lstride);
+  stage_end(h, w, VDWXC_STAGE_GRAD_Z);
+  stage_begin(h, w);
   hipLaunchKernelGGL((k_grad_y<double, kEPT>), dim3((h->n3 + h->gy.tile - 1) / h->gy.tile, h->n1), dim3(h->gy.nthr),
-                     h->gy.lds, h->stream, F2, F3, h->d_tw64[1], h->geo, h->plan[1], h->gy.tile, h->gy.lstride);
-  stage_end(h, VDWXC_STAGE_GRAD_Y);
-  stage_begin(h);
+                     h->gy.lds, h->stream, F2, F3, h->tw[1]->d64, h->geo, h->plan[1], h->gy.tile, h->gy.lstride);
+  stage_end(h, w, VDWXC_STAGE_GRAD_Y);
+  stage_begin(h, w);
   hipLaunchKernelGGL((k_grad_x<double, kEPT>), dim3((h->n3 + h->gx.tile - 1) / h->gx.tile, h->n2), dim3(h->gx.nthr),
-                     h->gx.lds, h->stream, F3, out, h->d_tw64[0], h->geo, h->plan[0], h->gx.tile, h->gx.lstride);
-  stage_end(h, VDWXC_STAGE_GRAD_X);
+                     h->gx.lds, h->stream, F3, out, h->tw[0]->d64, h->geo, h->plan[0], h->gx.tile, h->gx.lstride);
+  stage_end(h, w, VDWXC_STAGE_GRAD_X);
 }
 
 // v -= spectral divergence of 2 S grad n, one axis at a time (k_div_z, k_div_y, k_div_x); the
 // intermediate real fields sit in the work buffers ([3][N] in A, [2][N] in B)
 template <typename T>
-void enqueue_divergence(vdwxc_ctx* h, const double* S, const double* grad, double* v) {
+void enqueue_divergence(vdwxc_ctx* h, const Work& w, const double* S, const double* grad, double* v) {
   const Launch& Lz = Prec<T>::div(h, 2);
   const Launch& Ly = Prec<T>::div(h, 1);
   const Launch& Lx = Prec<T>::div(h, 0);
-  T* F3 = static_cast<T*>(h->d_A);
-  T* F2 = static_cast<T*>(h->d_B);
-  stage_begin(h);
+  T* F3 = static_cast<T*>(w.A);
+  T* F2 = static_cast<T*>(w.B);
+  stage_begin(h, w);
   hipLaunchKernelGGL((k_div_z<T, kEPT>), dim3((h->n2 + Lz.tile - 1) / Lz.tile, h->n1), dim3(Lz.nthr), Lz.lds,
                      h->stream, S, grad, F3, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
-  stage_end(h, VDWXC_STAGE_DIV_Z);
-  stage_begin(h);
+  stage_end(h, w, VDWXC_STAGE_DIV_Z);
+  stage_begin(h, w);
   hipLaunchKernelGGL((k_div_y<T, kEPT>), dim3((h->n3 + Ly.tile - 1) / Ly.tile, h->n1), dim3(Ly.nthr), Ly.lds,
                      h->stream, F3, F2, Prec<T>::tw(h, 1), h->geo, h->plan[1], Ly.tile, Ly.lstride);
-  stage_end(h, VDWXC_STAGE_DIV_Y);
-  stage_begin(h);
+  stage_end(h, w, VDWXC_STAGE_DIV_Y);
+  stage_begin(h, w);
   hipLaunchKernelGGL((k_div_x<T, kEPT>), dim3((h->n3 + Lx.tile - 1) / Lx.tile, h->n2), dim3(Lx.nthr), Lx.lds,
                      h->stream, F2, v, Prec<T>::tw(h, 0), h->geo, h->plan[0], Lx.tile, Lx.lstride);
-  stage_end(h, VDWXC_STAGE_DIV_X);
+  stage_end(h, w, VDWXC_STAGE_DIV_X);
 }
 
 // the five steps: theta + z FFT, y FFT, x FFT + contraction + inverse x, inverse y, inverse z +
 // derivatives; then the energy sum
 template <typename T>
-void enqueue_main(vdwxc_ctx* h, const double* n, const double* sig, bool sig_from_grad, double* dedn,
+void enqueue_main(vdwxc_ctx* h, const Work& w, const double* n, const double* sig, bool sig_from_grad, double* dedn,
                   double* dedsig, double* energy) {
   using T2 = typename Cx<T>::type;
   const Launch& Lz = Prec<T>::z(h);
   const Launch& Lx = Prec<T>::x(h);
-  T2* A = static_cast<T2*>(h->d_A);
-  T2* B = static_cast<T2*>(h->d_B);
+  T2* A = static_cast<T2*>(w.A);
+  T2* B = static_cast<T2*>(w.B);
+  const TableEntry& tb = *h->tab;
   dim3 zgrid((h->n2 + Lz.tile - 1) / Lz.tile, h->n1);
-  stage_begin(h);
+  stage_begin(h, w);
   const size_t lds_theta = Prec<T>::theta_lds(h), lds_asm = Prec<T>::asm_lds(h);
-  Quad<T>* state = static_cast<Quad<T>*>(h->d_state);
+  Quad<T>* state = static_cast<Quad<T>*>(w.state);
   if (sig_from_grad)
     hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, true>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A, state,
-                       h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
+                       w.flag, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
   else
     hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, false>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A, state,
-                       h->d_flag, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
-  stage_end(h, VDWXC_STAGE_THETA_ZFWD);
-  enqueue_ypass<T>(h, h->M, -1, VDWXC_STAGE_Y_FWD);
-  stage_begin(h);
+                       w.flag, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
+  stage_end(h, w, VDWXC_STAGE_THETA_ZFWD);
+  enqueue_ypass<T>(h, w, h->M, -1, VDWXC_STAGE_Y_FWD);
+  stage_begin(h, w);
   bool launched = false;
   if constexpr (sizeof(T) == 4) {
     if (h->x_capped) {
       hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 4>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream,
-                         B, Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+                         B, Prec<T>::table(h), w.partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
       launched = true;
     }
   }
   if (!launched)
     hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 1>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
-                       Prec<T>::table(h), h->d_partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
-  stage_end(h, VDWXC_STAGE_X_CONTRACT);
-  enqueue_ypass<T>(h, h->M, +1, VDWXC_STAGE_Y_INV);
-  stage_begin(h);
+                       Prec<T>::table(h), w.partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+  stage_end(h, w, VDWXC_STAGE_X_CONTRACT);
+  enqueue_ypass<T>(h, w, h->M, +1, VDWXC_STAGE_Y_INV);
+  stage_begin(h, w);
   const Launch& La = Prec<T>::za(h);
   const dim3 agrid((h->n2 + La.tile - 1) / La.tile, h->n1);
   const double N = double(h->n1) * h->n2 * h->n3;
   hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, asm_pb<T>()>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state, dedn,
-                     dedsig, h->d_q, h->d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile, La.lstride,
-                     h->d_partials, h->n2 * h->h3, h->omega / (2.0 * N * N), h->d_flag, energy, La.sets);
-  stage_end(h, VDWXC_STAGE_Z_ASSEMBLE);
+                     dedsig, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile, La.lstride,
+                     w.partials, h->n2 * h->h3, h->omega / (2.0 * N * N), w.flag, energy, La.sets);
+  stage_end(h, w, VDWXC_STAGE_Z_ASSEMBLE);
 }
 
 vdwxc_status check_handle(vdwxc_ctx* h) {
@@ -582,37 +809,38 @@ vdwxc_status finish_launch(vdwxc_ctx* h) {
   return VDWXC_OK;
 }
 
-vdwxc_status run_partials(vdwxc_ctx* h, const double* n, const double* sigma, double* dedn, double* dedsig,
-                          double* energy_dev) {
+vdwxc_status run_partials(vdwxc_ctx* h, const Work& w, const double* n, const double* sigma, double* dedn,
+                          double* dedsig, double* energy_dev) {
   HIP_TRY(h, hipSetDevice(h->device));
   if (h->precision == VDWXC_FP64)
-    enqueue_main<double>(h, n, sigma, false, dedn, dedsig, energy_dev);
+    enqueue_main<double>(h, w, n, sigma, false, dedn, dedsig, energy_dev);
   else
-    enqueue_main<float>(h, n, sigma, false, dedn, dedsig, energy_dev);
+    enqueue_main<float>(h, w, n, sigma, false, dedn, dedsig, energy_dev);
   return finish_launch(h);
 }
 
-vdwxc_status run_potential(vdwxc_ctx* h, const double* n, const double* grad, double* v, double* energy_dev) {
+vdwxc_status run_potential(vdwxc_ctx* h, const Work& w, const double* n, const double* grad, double* v,
+                           double* energy_dev) {
   HIP_TRY(h, hipSetDevice(h->device));
   const double* g = grad;
   if (!g) {
     // the gradient feeds q0, so it is taken in FP64 in both precisions
-    enqueue_gradient(h, n, h->d_G);
-    g = h->d_G;
+    enqueue_gradient(h, w, n, w.G);
+    g = w.G;
   }
   if (h->precision == VDWXC_FP64) {
-    enqueue_main<double>(h, n, g, true, v, h->d_S, energy_dev);
-    enqueue_divergence<double>(h, h->d_S, g, v);
+    enqueue_main<double>(h, w, n, g, true, v, w.S, energy_dev);
+    enqueue_divergence<double>(h, w, w.S, g, v);
   } else {
-    enqueue_main<float>(h, n, g, true, v, h->d_S, energy_dev);
-    enqueue_divergence<float>(h, h->d_S, g, v);
+    enqueue_main<float>(h, w, n, g, true, v, w.S, energy_dev);
+    enqueue_divergence<float>(h, w, w.S, g, v);
   }
   return finish_launch(h);
 }
 
 vdwxc_status read_energy(vdwxc_ctx* h, double* energy_host) {
   HIP_TRY(h, hipMemcpyAsync(h->h_energy, h->d_energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->h_flag, h->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->h_flag, h->work.flag + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   if (*h->h_flag) return fail(h, VDWXC_EINVAL, "density or gradient input contains NaN");
   *energy_host = *h->h_energy;
@@ -642,12 +870,14 @@ const char* vdwxc_strerror(vdwxc_status s) {
 
 const char* vdwxc_last_error(vdwxc_handle h) { return h ? h->last_error.c_str() : g_init_error.c_str(); }
 
-size_t vdwxc_workspace_bytes(const int grid[3], vdwxc_precision precision, int nq) {
+size_t vdwxc_workspace_bytes_m(const int grid[3], vdwxc_precision precision, int nq) {
   if (!grid || grid[0] < 1 || grid[1] < 1 || grid[2] < 1 || nq < 1) return 0;
-  const size_t N = size_t(grid[0]) * grid[1] * grid[2];
-  const size_t cplx = complex_buffer_bytes(grid[0], grid[1], grid[2], precision, nq);
-  return 2 * cplx + 4 * N * sizeof(double) + N * state_bytes(precision) +
-         size_t(grid[1]) * (grid[2] / 2 + 1) * sizeof(double) + 64;
+  if (precision != VDWXC_FP64 && precision != VDWXC_FP32_MIXED) return 0;
+  return workspace_layout(grid[0], grid[1], grid[2], precision, nq).total;
+}
+
+size_t vdwxc_workspace_bytes(const int grid[3], vdwxc_precision precision) {
+  return vdwxc_workspace_bytes_m(grid, precision, kMaxQ);
 }
 
 vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
@@ -667,6 +897,13 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     if (!std::isfinite(qmesh[i]) || !(qmesh[i] > 0.0) || (i > 0 && !(qmesh[i] > qmesh[i - 1])))
       return fail(nullptr, VDWXC_ETABLE, "q-mesh must be positive and strictly increasing");
   }
+  // q0 saturates at a = 5 (appendix); a mesh ending below it would leave q0 in (q_M-1, 5] outside
+  // every spline interval
+  if (!(qmesh[nq - 1] >= kSatA * (1.0 - 1e-12)))
+    return fail(nullptr, VDWXC_ETABLE, "q-mesh must reach the saturation value q0 = 5 (last point >= 5)");
+  // the contraction addresses the pair table with 32-bit byte offsets
+  if (double(pair_table_bytes(VDWXC_FP64, nk)) >= 2147483648.0)
+    return fail(nullptr, VDWXC_ETABLE, "kernel table has too many k nodes (its pair table must stay below 2 GiB)");
   const size_t tsz = size_t(nk) * nq * nq;
   for (size_t i = 0; i < tsz; ++i)
     if (!std::isfinite(table[i])) return fail(nullptr, VDWXC_ETABLE, "kernel table contains NaN/inf");
@@ -780,64 +1017,19 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   };
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) return bail(e, "hipGetDevice");
-  std::vector<double> mm;
-  natural_spline_moments(h->qmesh, mm);
-  if ((e = upload(&h->d_q, h->qmesh.data(), nq)) != hipSuccess) return bail(e, "q-mesh upload");
-  if ((e = upload(&h->d_mm, mm.data(), mm.size())) != hipSuccess) return bail(e, "spline upload");
-  {
-    // per unordered pair p = (a <= b) and node j: T_j and T_j+1 - T_j (0 at the last node);
-    // pairs 2g and 2g+1 share entry (g, j) = (T_j(2g), T_j(2g+1), D_j(2g), D_j(2g+1)), stored
-    // chunk-major at [g / kXChunk][j][g % kXChunk] (the contraction reads a chunk's entries of
-    // one node together).  Pairs with a or b >= nq stay zero.
-    constexpr int kGroups = kNumPairs / 2, kChunks = (kGroups + kXChunk - 1) / kXChunk;
-    const size_t tn = size_t(kChunks) * kXChunk * nk;
-    std::vector<Quad<double>> t64(tn, Quad<double>{0.0, 0.0, 0.0, 0.0});
-    for (int a = 0; a < nq; ++a)
-      for (int b = a; b < nq; ++b) {
-        const int pr = pair_index(a, b);
-        for (int j = 0; j < nk; ++j) {
-          const double tj = table[(size_t(j) * nq + a) * nq + b];
-          const double dj = j + 1 < nk ? table[(size_t(j + 1) * nq + a) * nq + b] - tj : 0.0;
-          const int grp = pr / 2;
-          Quad<double>& q = t64[(size_t(grp / kXChunk) * nk + j) * kXChunk + grp % kXChunk];
-          if (pr % 2 == 0) {
-            q.x = tj;
-            q.z = dj;
-          } else {
-            q.y = tj;
-            q.w = dj;
-          }
-        }
-      }
-    if (precision == VDWXC_FP64) {
-      if ((e = upload(&h->d_table64, t64.data(), tn)) != hipSuccess) return bail(e, "table upload");
-    } else {
-      std::vector<Quad<float>> t32(tn);
-      for (size_t i = 0; i < tn; ++i)
-        t32[i] = Quad<float>{float(t64[i].x), float(t64[i].y), float(t64[i].z), float(t64[i].w)};
-      if ((e = upload(&h->d_table32, t32.data(), tn)) != hipSuccess) return bail(e, "table upload");
-    }
-  }
-  for (int a = 0; a < 3; ++a) {
-    auto t64 = twiddles<double2, double>(n[a]);
-    auto t32 = twiddles<float2, float>(n[a]);
-    if ((e = upload(&h->d_tw64[a], t64.data(), t64.size())) != hipSuccess) return bail(e, "twiddle upload");
-    if ((e = upload(&h->d_tw32[a], t32.data(), t32.size())) != hipSuccess) return bail(e, "twiddle upload");
-  }
-  const size_t N = size_t(h->n1) * h->n2 * h->n3;
+  if ((e = acquire_table(h->device, precision, nq, qmesh, nk, kmax, table, &h->tab)) != hipSuccess)
+    return bail(e, "kernel table upload");
+  for (int a = 0; a < 3; ++a)
+    if ((e = acquire_twiddles(h->device, n[a], &h->tw[a])) != hipSuccess) return bail(e, "twiddle upload");
   h->buf_bytes = complex_buffer_bytes(h->n1, h->n2, h->n3, precision, nq);
-  if ((e = hipMalloc(&h->d_A, h->buf_bytes)) != hipSuccess) return bail(e, "work buffer A");
-  if ((e = hipMalloc(&h->d_B, h->buf_bytes)) != hipSuccess) return bail(e, "work buffer B");
-  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_S), N * sizeof(double))) != hipSuccess) return bail(e, "dE/dsigma buffer");
-  if ((e = hipMalloc(&h->d_state, N * state_bytes(precision))) != hipSuccess) return bail(e, "spline state buffer");
-  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_G), 3 * N * sizeof(double))) != hipSuccess) return bail(e, "gradient buffer");
-  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_partials), size_t(h->n2) * h->h3 * sizeof(double))) != hipSuccess)
-    return bail(e, "energy partials");
+  const Layout lay = workspace_layout(h->n1, h->n2, h->n3, precision, nq);
+  h->ws_bytes = lay.total;
+  if ((e = hipMalloc(&h->d_ws, h->ws_bytes)) != hipSuccess) return bail(e, "work buffers");
+  h->work = carve(h->d_ws, lay);
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_energy), sizeof(double))) != hipSuccess) return bail(e, "energy");
-  // [0]: raised by the theta pass, [1]: the last evaluation's result (see energy_reduce_block)
-  if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_flag), 2 * sizeof(int))) != hipSuccess) return bail(e, "flag");
-  if ((e = hipMemsetAsync(h->d_flag, 0, 2 * sizeof(int), h->stream)) != hipSuccess ||
-      (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+  // flag [0]: raised by the theta pass, [1]: the last evaluation's result (see energy_reduce_block)
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, h->stream, h->work.flag);
+  if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(h->stream)) != hipSuccess)
     return bail(e, "flag");
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&h->h_energy), sizeof(double), hipHostMallocDefault)) != hipSuccess)
     return bail(e, "pinned energy");
@@ -921,7 +1113,8 @@ vdwxc_status vdwxc_init(vdwxc_handle* out, const int grid[3], const double cell[
                         vdwxc_precision precision, const char* kernel_table_path, void* hip_stream) {
   if (!out) return fail(nullptr, VDWXC_EINVAL, "out must not be NULL");
   *out = nullptr;
-  if (!kernel_table_path) return fail(nullptr, VDWXC_EINVAL, "kernel_table_path must not be NULL");
+  const std::string path = kernel_table_path ? std::string(kernel_table_path) : default_table_path();
+  kernel_table_path = path.c_str();
   FILE* f = std::fopen(kernel_table_path, "rb");
   if (!f) return fail(nullptr, VDWXC_ETABLE, std::string("cannot open kernel table ") + kernel_table_path);
   char magic[4];
@@ -948,7 +1141,7 @@ vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double
   if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
   if (!n || !sigma || !dedn || !dedsigma || !energy_dev)
     return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
-  return run_partials(h, n, sigma, dedn, dedsigma, energy_dev);
+  return run_partials(h, h->work, n, sigma, dedn, dedsigma, energy_dev);
 }
 
 vdwxc_status vdwxc_calculate(vdwxc_handle h, const double* n, const double* sigma, double* dedn, double* dedsigma,
@@ -956,7 +1149,7 @@ vdwxc_status vdwxc_calculate(vdwxc_handle h, const double* n, const double* sigm
   if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
   if (!n || !sigma || !dedn || !dedsigma || !energy_host)
     return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
-  vdwxc_status st = run_partials(h, n, sigma, dedn, dedsigma, h->d_energy);
+  vdwxc_status st = run_partials(h, h->work, n, sigma, dedn, dedsigma, h->d_energy);
   if (st != VDWXC_OK) return st;
   return read_energy(h, energy_host);
 }
@@ -965,14 +1158,14 @@ vdwxc_status vdwxc_calculate_potential_async(vdwxc_handle h, const double* n, co
                                              double* energy_dev) {
   if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
   if (!n || !v || !energy_dev) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
-  return run_potential(h, n, grad_n, v, energy_dev);
+  return run_potential(h, h->work, n, grad_n, v, energy_dev);
 }
 
 vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const double* grad_n, double* v,
                                        double* energy_host) {
   if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
   if (!n || !v || !energy_host) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
-  vdwxc_status st = run_potential(h, n, grad_n, v, h->d_energy);
+  vdwxc_status st = run_potential(h, h->work, n, grad_n, v, h->d_energy);
   if (st != VDWXC_OK) return st;
   return read_energy(h, energy_host);
 }

@@ -18,6 +18,7 @@ metal-core/ligand-shell nanoparticle in a large cell, Sec. 4-5):
 * ``slater_192``        - 192^3 grid, 28 Angstrom cube, 600 Slater blobs.
 * ``serving``           - grid N in {48, 64, 96, 128, 160}, cell N*0.15625 Angstrom, 50-400 blobs.
 * ``nanoparticle_512``  - 512^3 grid, 48 Angstrom cube, 576 core + 9120 shell blobs.
+* ``nanoparticle_slab`` - any grid at the nanoparticle's spacing, its blob model scaled to the cell.
 """
 from __future__ import annotations
 
@@ -152,18 +153,26 @@ def gaussian_pair_density(grid, length_bohr: float, centres_bohr, width_bohr: fl
     return n, grad
 
 
-def slater_blob_density(grid, length_bohr: float, centres_bohr: np.ndarray, zetas: np.ndarray,
+def _axis_lengths(length_bohr):
+    """(L1, L2, L3) of a rectangular cell from one length (cube) or three."""
+    if np.ndim(length_bohr) == 0:
+        return (float(length_bohr),) * 3
+    return tuple(float(x) for x in length_bohr)
+
+
+def slater_blob_density(grid, length_bohr, centres_bohr: np.ndarray, zetas: np.ndarray,
                         device: str = "cpu", progress=None):
-    """n = sum_i (zeta_i^3/pi) exp(-2 zeta_i d_i) on a periodic cubic cell, d_i the minimum-image
-    distance; each blob is cut off where exp(-2 zeta d) < 1e-20.  Returns torch float64 tensors
-    (n [N1,N2,N3], grad [3,N1,N2,N3]) on ``device``.  Each blob is added on its own sub-box of
-    the grid, in blob order, so the bytes are reproducible for a given device.  ``progress``, if
-    given, is called as progress(done, total) after every 1000 blobs."""
+    """n = sum_i (zeta_i^3/pi) exp(-2 zeta_i d_i) on a periodic rectangular cell (``length_bohr``:
+    one edge length for a cube, or three), d_i the minimum-image distance; each blob is cut off
+    where exp(-2 zeta d) < 1e-20.  Returns torch float64 tensors (n [N1,N2,N3], grad [3,N1,N2,N3])
+    on ``device``.  Each blob is added on its own sub-box of the grid, in blob order, so the bytes
+    are reproducible for a given device.  ``progress``, if given, is called as
+    progress(done, total) after every 1000 blobs."""
     torch = _torch()
     n1, n2, n3 = (int(g) for g in grid)
     dims = (n1, n2, n3)
-    L = float(length_bohr)
-    h = [L / g for g in dims]
+    Ls = _axis_lengths(length_bohr)
+    h = [Lx / g for Lx, g in zip(Ls, dims)]
     dev = torch.device(device)
     n = torch.zeros(dims, dtype=torch.float64, device=dev)
     grad = torch.zeros((3,) + dims, dtype=torch.float64, device=dev)
@@ -174,7 +183,7 @@ def slater_blob_density(grid, length_bohr: float, centres_bohr: np.ndarray, zeta
         dcut = SLATER_CUTOFF_EXPONENT / (2.0 * z)
         idx, dist = [], []
         for ax in range(3):
-            g = dims[ax]
+            g, L = dims[ax], Ls[ax]
             lo = math.floor((c[ax] - dcut) / h[ax])
             hi = math.ceil((c[ax] + dcut) / h[ax])
             if hi - lo + 1 >= g:
@@ -268,6 +277,33 @@ def _blobs_nanoparticle(rng, length_bohr):
     return centres, zetas
 
 
+# grid spacing of the nanoparticle workload: 48 Angstrom over 512 points
+NANO_SPACING = 48.0 * ANGSTROM / 512
+
+
+def _blobs_nanoparticle_scaled(rng, lengths_bohr):
+    """The nanoparticle's core + shell blob model squeezed into a rectangular cell: positions drawn
+    as in `_blobs_nanoparticle` (ball of 8 Angstrom, shell 8-20 Angstrom), each axis scaled by
+    L_axis / 48 Angstrom about the cell centre, and the blob counts scaled by the cell's volume
+    relative to the 48 Angstrom cube (at least one of each kind)."""
+    L0 = 48.0 * ANGSTROM
+    s = np.asarray(lengths_bohr, dtype=np.float64) / L0
+    frac = float(np.prod(s))
+    ncore, nshell = max(1, round(576 * frac)), max(1, round(9120 * frac))
+
+    def ball(count, r0, r1):
+        v = rng.normal(size=(count, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        u = rng.uniform(size=count)
+        r = (r0 ** 3 + u * (r1 ** 3 - r0 ** 3)) ** (1.0 / 3.0)
+        return v * r[:, None]
+    core = ball(ncore, 0.0, 8.0 * ANGSTROM)
+    shell = ball(nshell, 8.0 * ANGSTROM, 20.0 * ANGSTROM)
+    centres = np.concatenate([core, shell]) * s[None, :] + 0.5 * np.asarray(lengths_bohr)[None, :]
+    zetas = np.concatenate([rng.uniform(1.9, 2.1, ncore), rng.uniform(0.9, 1.1, nshell)])
+    return centres, zetas
+
+
 @dataclass
 class Workload:
     name: str
@@ -284,6 +320,9 @@ class Workload:
         """(n, grad) as torch float64 tensors on ``device`` (``progress``: see slater_blob_density)."""
         torch = _torch()
         L = float(self.cell[0, 0])
+        if self.name.startswith("nanoparticle_slab"):
+            return slater_blob_density(self.grid, np.diag(self.cell), self.centres, self.zetas, device=device,
+                                       progress=progress)
         if self.name.startswith("serving_"):
             return slater_blob_density_dense(self.grid, L, self.centres, self.zetas, device=device)
         if self.name == "two_gaussians_32":
@@ -294,8 +333,14 @@ class Workload:
         return slater_blob_density(self.grid, L, self.centres, self.zetas, device=device, progress=progress)
 
 
-def workload(name: str, grid_n: int | None = None, seed_offset: int = 0) -> Workload:
-    """The named synthetic workloads; RNG numpy.random.default_rng(17030699 + index)."""
+def workload(name: str, grid_n: int | None = None, seed_offset: int = 0, grid=None) -> Workload:
+    """The named synthetic workloads; RNG numpy.random.default_rng(17030699 + index).
+
+    ``nanoparticle_slab`` takes ``grid`` (N1, N2, N3): a rectangular cell at the nanoparticle's
+    grid spacing (48 Angstrom / 512), N_i points along axis i, holding the nanoparticle's
+    core + shell blob model scaled to the cell (`_blobs_nanoparticle_scaled`).  (64, 512, 512) is
+    one GPU's x-slab of the 512^3 grid split eight ways, (512, 64, 64) a pencil along x: between
+    them they exercise every 512-point axis of the full-size workload at sizes the oracle finishes."""
     if name == "two_gaussians_32":
         return Workload(name, (32, 32, 32), cubic_cell(8.0 * ANGSTROM))
     if name == "slater_128":
@@ -320,6 +365,12 @@ def workload(name: str, grid_n: int | None = None, seed_offset: int = 0) -> Work
         rng = np.random.default_rng(SEED_BASE + 4 + seed_offset)
         c, z = _blobs_nanoparticle(rng, L)
         return Workload(name, (512, 512, 512), cubic_cell(L), c, z)
+    if name == "nanoparticle_slab":
+        dims = tuple(int(g) for g in grid)
+        lengths = [NANO_SPACING * g for g in dims]
+        rng = np.random.default_rng(SEED_BASE + 5 + seed_offset)
+        c, z = _blobs_nanoparticle_scaled(rng, lengths)
+        return Workload(f"nanoparticle_slab_{dims[0]}x{dims[1]}x{dims[2]}", dims, np.diag(lengths), c, z)
     raise KeyError(name)
 
 

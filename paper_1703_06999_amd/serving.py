@@ -10,10 +10,15 @@ with them; completions are detected with stream events and free their slot immed
 
 Every evaluation is deterministic (fixed-order reductions, no atomics), so a request's (E, v) is
 bitwise the same alone or in the mix.
+
+`submit` returns a `concurrent.futures.Future` that resolves to the finished Request (its `energy`
+and `v` device tensors complete), or fails at once with ValueError when the request's handle alone
+needs more than the whole HBM budget (it could never be admitted).
 """
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import time
 from dataclasses import dataclass, field
 
@@ -37,6 +42,7 @@ class Request:
     energy: torch.Tensor | None = None
     v: torch.Tensor | None = None
     slot: int | None = None
+    future: concurrent.futures.Future | None = None
 
     @property
     def latency(self) -> float:
@@ -65,6 +71,7 @@ class Server:
         self.resident = 0.0
         self.queue: collections.deque = collections.deque()
         self.done: list[Request] = []
+        self.rejected: list[Request] = []
         self.max_concurrent = 0
         self.peak_resident = 0.0
 
@@ -75,22 +82,27 @@ class Server:
     def _key(self, req):
         return (tuple(req.grid), tuple(np.asarray(req.cell, dtype=np.float64).ravel().round(12)))
 
-    def _handle_for(self, slot: _Slot, req: Request):
-        """The slot's handle for this grid/cell, creating it if the budget allows (evicting the
-        slot's idle handles of other shapes first if needed); None if it cannot fit now."""
+    def _handle_for(self, slot: _Slot, req: Request, free_slots):
+        """The slot's handle for this grid/cell, creating it if the budget allows; None if it cannot
+        fit now.  To make room it evicts idle handles (this slot's first, then those of the other
+        free slots), but only when evicting them does make room: otherwise nothing is evicted and
+        the resident plans and tables stay."""
         key = self._key(req)
         h = slot.handles.get(key)
         if h is not None:
             return h
         need = self._cost(req.grid)
         if self.resident + need > self.budget:
-            for k in list(slot.handles):
+            order = [slot] + [s for s in free_slots if s is not slot]
+            victims = [(s, k) for s in order for k in s.handles]
+            freeable = sum(self._cost(k[0]) for _, k in victims)
+            if self.resident - freeable + need > self.budget:
+                return None
+            for s, k in victims:
                 self.resident -= self._cost(k[0])
-                slot.handles.pop(k).close()
+                s.handles.pop(k).close()
                 if self.resident + need <= self.budget:
                     break
-        if self.resident + need > self.budget:
-            return None
         with torch.cuda.stream(slot.stream):
             h = vdwxc.Functional(req.grid, req.cell, flavour=self.flavour, precision=self.precision,
                                  table=self.table, stream=slot.stream)
@@ -124,8 +136,18 @@ class Server:
         return made
 
     # ---- scheduling --------------------------------------------------------------------------
-    def submit(self, req: Request):
+    def submit(self, req: Request) -> concurrent.futures.Future:
+        """Queue a request; the returned Future resolves to the finished Request."""
+        req.future = concurrent.futures.Future()
+        need = self._cost(req.grid)
+        if need > self.budget:
+            req.future.set_exception(ValueError(
+                f"request {req.rid}: grid {tuple(req.grid)} needs {need / 1e9:.3f} GB of work buffers, more than "
+                f"the whole HBM budget of {self.budget / 1e9:.3f} GB"))
+            self.rejected.append(req)
+            return req.future
         self.queue.append(req)
+        return req.future
 
     def _start(self, slot: _Slot, req: Request, h, now: float):
         req.admitted = now
@@ -147,6 +169,8 @@ class Server:
             if s.busy is not None and s.event.query():
                 s.busy.finished = now
                 self.done.append(s.busy)
+                if s.busy.future is not None:
+                    s.busy.future.set_result(s.busy)
                 s.busy, s.event = None, None
         while self.queue:
             req = self.queue[0]
@@ -158,7 +182,7 @@ class Server:
             free.sort(key=lambda s: key not in s.handles)
             h = None
             for s in free:
-                h = self._handle_for(s, req)
+                h = self._handle_for(s, req, free)
                 if h is not None:
                     self._start(s, req, h, now)
                     break
@@ -184,10 +208,13 @@ class Server:
                 time.sleep(poll_interval)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        if not self.done:
+            return {"requests": 0, "rejected": len(self.rejected), "wall_s": wall}
         lat = np.array([r.latency for r in self.done])
         pts = sum(int(np.prod(r.grid)) for r in self.done)
         return {
             "requests": len(self.done),
+            "rejected": len(self.rejected),
             "wall_s": wall,
             "req_per_s": len(self.done) / wall,
             "pts_per_s": pts / wall,

@@ -38,7 +38,8 @@ SIGNATURES = {
     "vdwxc_calculate_potential": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp]),
     "vdwxc_calculate_potential_async": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                        ctypes.c_void_p]),
-    "vdwxc_workspace_bytes": (ctypes.c_size_t, [_ip, ctypes.c_int, ctypes.c_int]),
+    "vdwxc_workspace_bytes": (ctypes.c_size_t, [_ip, ctypes.c_int]),
+    "vdwxc_workspace_bytes_m": (ctypes.c_size_t, [_ip, ctypes.c_int, ctypes.c_int]),
     "vdwxc_set_stream": (ctypes.c_int, [_h, ctypes.c_void_p]),
     "vdwxc_print": (ctypes.c_int, [_h]),
     "vdwxc_finalize": (ctypes.c_int, [ctypes.POINTER(_h)]),
@@ -87,9 +88,10 @@ def _check(status: int, handle=None):
 
 
 def workspace_bytes(grid, precision="fp64", nq: int = 20) -> int:
+    """Device bytes of a handle's work buffers (vdwxc_workspace_bytes_m)."""
     g = (ctypes.c_int * 3)(*[int(x) for x in grid])
-    return int(lib().vdwxc_workspace_bytes(g, PRECISIONS[precision] if isinstance(precision, str) else int(precision),
-                                           int(nq)))
+    return int(lib().vdwxc_workspace_bytes_m(g, PRECISIONS[precision] if isinstance(precision, str) else int(precision),
+                                             int(nq)))
 
 
 def _cell_array(cell):

@@ -44,6 +44,11 @@ def test_workspace_bytes():
     nk = 64 * 64 * 33
     assert w64 >= 2 * 20 * nk * 16 and w32 >= 2 * 20 * nk * 8 and w32 < w64
     assert vdwxc.workspace_bytes((0, 4, 4)) == 0
+    L = vdwxc.lib()
+    g = (ctypes.c_int * 3)(64, 64, 64)
+    assert L.vdwxc_workspace_bytes(g, vdwxc.FP64) == w64          # N_alpha = 20
+    assert L.vdwxc_workspace_bytes_m(g, vdwxc.FP64, 10) < w64      # fewer fields, smaller buffers
+    assert L.vdwxc_workspace_bytes(g, 7) == 0                      # unknown precision
 
 
 KT = inputs.synthetic_kernel_table()
@@ -89,6 +94,15 @@ def test_init_rejects_bad_tables():
     t[0, 0, 0] = np.nan
     assert init_status((4, 4, 4), cell, table=inputs.KernelTable(KT.qmesh, KT.kmax, t))[0] == vdwxc.ETABLE
     assert init_status((4, 4, 4), cell, kmax=-1.0)[0] == vdwxc.ETABLE
+    # the q-mesh must reach the saturation value 5 of q0
+    short = inputs.synthetic_kernel_table(qmesh=inputs.log_qmesh(20, qcut=4.0))
+    st, msg = init_status((4, 4, 4), cell, table=short)
+    assert st == vdwxc.ETABLE and "saturation" in msg
+    # a pair table of 2 GiB or more cannot be addressed by the contraction
+    q4 = inputs.log_qmesh(4)
+    big = inputs.KernelTable(q4, 40.0, np.zeros((700_000, 4, 4)))
+    st, msg = init_status((4, 4, 4), cell, table=big)
+    assert st == vdwxc.ETABLE and "k nodes" in msg
     assert init_status((4, 4, 4), cell, flavour=7)[0] == vdwxc.EINVAL
     assert init_status((4, 4, 4), cell, precision=9)[0] == vdwxc.EINVAL
 
@@ -108,7 +122,28 @@ def test_init_from_file_errors(tmp_path):
     data = p2.read_bytes()
     p2.write_bytes(data[: len(data) // 2])
     assert L.vdwxc_init(ctypes.byref(h), g, c, 1, 0, str(p2).encode(), None) == vdwxc.ETABLE
-    assert L.vdwxc_init(ctypes.byref(h), g, c, 1, 0, None, None) == vdwxc.EINVAL
+
+
+def test_null_table_path_reads_the_default_table(tmp_path, monkeypatch):
+    """NULL path: the file named by VDWXC_KERNEL_TABLE, else the one the build writes next to the
+    library (the errors are reported before any device work)."""
+    L = vdwxc.lib()
+    h = ctypes.c_void_p()
+    g = (ctypes.c_int * 3)(4, 4, 4)
+    c = (ctypes.c_double * 9)(5, 0, 0, 0, 5, 0, 0, 0, 5)
+    monkeypatch.setenv("VDWXC_KERNEL_TABLE", str(tmp_path / "none.vdwk"))
+    assert L.vdwxc_init(ctypes.byref(h), g, c, 1, 0, None, None) == vdwxc.ETABLE
+    assert "none.vdwk" in L.vdwxc_last_error(None).decode()
+    monkeypatch.delenv("VDWXC_KERNEL_TABLE")
+    from paper_1703_06999_amd import build
+    assert os.path.exists(build.DEFAULT_TABLE)
+    back = inputs.KernelTable.load(build.DEFAULT_TABLE)
+    assert np.array_equal(back.table, KT.table) and np.array_equal(back.qmesh, KT.qmesh)
+    st = L.vdwxc_init(ctypes.byref(h), g, c, 1, 0, None, None)
+    if st == vdwxc.OK:   # a GPU is present
+        assert L.vdwxc_finalize(ctypes.byref(h)) == vdwxc.OK
+    else:                # the table was read; only the device is missing
+        assert st == vdwxc.EDEVICE, L.vdwxc_last_error(None)
 
 
 def test_table_file_round_trip(tmp_path):

