@@ -644,14 +644,11 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
       if ((cc) * kXChunk + i < kGroups) buffer_load_quad(trs, joff + i * kQ, tcur, (dst)[i]);     \
     tcur += cstride;                                                                              \
   } while (0)
-    // chunks past the pairs of the q-mesh hold zeros: stop before them (M < 20)
-    const int nchunks = used_chunks(M, kXChunk);
     Quad<T> buf[2][kXChunk];
     VDWXC_TLOAD_CHUNK(buf[0], 0);
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-      if (c >= nchunks) break;
-      if (c + 1 < kChunks && c + 1 < nchunks) VDWXC_TLOAD_CHUNK(buf[(c + 1) & 1], c + 1);
+      if (c + 1 < kChunks) VDWXC_TLOAD_CHUNK(buf[(c + 1) & 1], c + 1);
 #pragma unroll
       for (int i = 0; i < kXChunk; ++i) {
         const int grp = c * kXChunk + i;
