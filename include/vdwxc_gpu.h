@@ -107,6 +107,20 @@ vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const do
 vdwxc_status vdwxc_calculate_potential_async(vdwxc_handle h, const double* n, const double* grad_n, double* v,
                                              double* energy_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): vdwxc_calculate_potential_async with the handle's work
+ * buffers replaced by a static array of 128 MiB that the library holds on each device until the
+ * process ends.  The call allocates nothing (no hipMalloc, hipFree or allocating library routine;
+ * per-stage timing events are not recorded) and enqueues the same kernels, so the results are
+ * bitwise those of vdwxc_calculate_potential_async.  Grids whose work memory
+ * (vdwxc_workspace_bytes_m) exceeds 128 MiB are rejected with VDWXC_EINVAL before any device work,
+ * e.g. 64^3 fits in both precisions and 96^3 in neither.  All calls on one device share the array
+ * and it keeps the last call's contents: calls that overlap on one device (other streams, other
+ * threads, other handles) race and give wrong results, so the caller orders them.  The handle
+ * must have been created on the device it runs on (vdwxc_init* records the array's address). */
+vdwxc_status vdwxc_calculate_potential_noalloc(vdwxc_handle h, const double* n, const double* grad_n, double* v,
+                                               double* energy_dev);
+
 /* As vdwxc_calculate but asynchronous: the energy goes to the device double energy_dev. */
 vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double* sigma, double* dedn,
                                    double* dedsigma, double* energy_dev);

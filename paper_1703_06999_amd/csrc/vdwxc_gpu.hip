@@ -148,6 +148,40 @@ std::vector<TwiddleEntry*> g_twiddles;
 
 }  // namespace
 
+// ---- static work memory of the allocation-free entry point ------------------------------------
+// vdwxc_calculate_potential_noalloc runs with its work buffers in this array instead of the
+// handle's own.  Each device the library runs on holds one copy of it until the process ends.  In
+// host code the name `scratch` is only a stand-in for the symbol, not a device address: the address
+// comes from hipGetSymbolAddress, taken once per device (with that device current) by the first
+// vdwxc_init* on it, and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// record the device address of `scratch` on `device` (the current device), once
+hipError_t ensure_scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 struct vdwxc_ctx {
   int n1 = 0, n2 = 0, n3 = 0, h3 = 0;
   double cell[9] = {0};
@@ -1017,6 +1051,7 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   };
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) return bail(e, "hipGetDevice");
+  if ((e = ensure_scratch_address(h->device)) != hipSuccess) return bail(e, "static work memory address");
   if ((e = acquire_table(h->device, precision, nq, qmesh, nk, kmax, table, &h->tab)) != hipSuccess)
     return bail(e, "kernel table upload");
   for (int a = 0; a < 3; ++a)
@@ -1168,6 +1203,24 @@ vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const do
   vdwxc_status st = run_potential(h, h->work, n, grad_n, v, h->d_energy);
   if (st != VDWXC_OK) return st;
   return read_energy(h, energy_host);
+}
+
+vdwxc_status vdwxc_calculate_potential_noalloc(vdwxc_handle h, const double* n, const double* grad_n, double* v,
+                                               double* energy_dev) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (!n || !v || !energy_dev) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  const Layout lay = workspace_layout(h->n1, h->n2, h->n3, h->precision, h->M);
+  if (lay.total > kScratchBytes)
+    return fail(h, VDWXC_EINVAL, "grid needs " + std::to_string(lay.total) + " bytes of work memory, more than the " +
+                                     std::to_string(kScratchBytes) + " of the static work memory");
+  void* base = scratch_address(h->device);
+  if (!base) return fail(h, VDWXC_ESTATE, "no static work memory address for this device");
+  Work w = carve(base, lay);
+  w.timed = false;   // taking a timing event may allocate
+  HIP_TRY(h, hipSetDevice(h->device));
+  // the array keeps the last call's contents: the NaN flags must start at zero
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, h->stream, w.flag);
+  return run_potential(h, w, n, grad_n, v, energy_dev);
 }
 
 const char* vdwxc_stage_name(int stage) {

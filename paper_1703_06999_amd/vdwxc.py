@@ -38,6 +38,8 @@ SIGNATURES = {
     "vdwxc_calculate_potential": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp]),
     "vdwxc_calculate_potential_async": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                        ctypes.c_void_p]),
+    "vdwxc_calculate_potential_noalloc": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                         ctypes.c_void_p]),
     "vdwxc_workspace_bytes": (ctypes.c_size_t, [_ip, ctypes.c_int]),
     "vdwxc_workspace_bytes_m": (ctypes.c_size_t, [_ip, ctypes.c_int, ctypes.c_int]),
     "vdwxc_set_stream": (ctypes.c_int, [_h, ctypes.c_void_p]),
@@ -190,6 +192,15 @@ class Functional:
         self._sync_stream()
         st = lib().vdwxc_calculate_potential_async(self._h, self._field(n, "n"), gp, self._field(v, "v"),
                                                    ctypes.c_void_p(energy.data_ptr()))
+        _check(st, self._h)
+
+    def potential_noalloc(self, n, grad, v, energy):
+        """As potential_async, with the work buffers in the library's static array (allocates
+        nothing; calls on one device must not overlap; grids up to 128 MiB of work memory)."""
+        gp = self._field(grad, "grad", 3) if grad is not None else ctypes.c_void_p(0)
+        self._sync_stream()
+        st = lib().vdwxc_calculate_potential_noalloc(self._h, self._field(n, "n"), gp, self._field(v, "v"),
+                                                     ctypes.c_void_p(energy.data_ptr()))
         _check(st, self._h)
 
     def enable_timing(self, enable: bool = True):
