@@ -325,6 +325,74 @@ __device__ __forceinline__ void lds_fft_stages(T2* buf, const AxisPlan& plan, in
   run_stages<7, EPT, DIR, PS, LIN>(buf, plan, n, cnt[6], s0, p, nlines, lstride, tw, tid, nthr);
 }
 
+// ---- 512-point lines: three radix-8 stages with per-thread constants ---------------------------
+// For n = 512 = 8 * 8 * 8 every stage has 64 butterflies per line, and a block of nthr threads
+// (a multiple of 64) gives thread t the butterfly column i = t mod 64 of lines t / 64 + c nthr / 64.
+// i is the same in all three stages and on every line of the thread, so are k = i mod p (p = 1, 8,
+// 64 before the stage) and with them every LDS offset and twiddle of the thread:
+//   reads of every stage, writes of the last:  i + 64 r
+//   writes of stage 1 (p = 1, k = 0):          8 i + r
+//   writes of stage 2 (p = 8, k = i mod 8):    8 (i - k) + k + 8 r
+//   twiddles of stage 2: exp(-+2 pi i r k / 64) = tw[8 r k];  of stage 3: exp(-+2 pi i r i / 512) = tw[r i]
+// so they are formed once per transform instead of once per butterfly and stage (the generic
+// stage above recomputes the line, column and k of every butterfly, then each address and the
+// twiddle index; that index arithmetic cost about as much as the butterfly itself).
+template <int MAXB, int DIR, int PS, typename T2>
+__device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, const T2* __restrict__ tw, int tid,
+                                           int nthr) {
+  int i = tid & 63;
+  // the offsets and twiddles below depend on the thread alone: without this the compiler shares
+  // them between the transforms of one kernel, or hoists them out of a caller's loop, and keeps
+  // them live (and the caller's registers spilled) in between
+  asm volatile("" : "+v"(i));
+  const int l0 = tid >> 6, lstep = nthr >> 6;
+  const int k2 = i & 7;
+  int ro[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) ro[r] = lidx<PS>(i + 64 * r);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    T2 w[8];
+    if (s > 0) {
+#pragma unroll
+      for (int r = 1; r < 8; ++r) {
+        w[r] = tw[s == 1 ? 8 * r * k2 : r * i];
+        if (DIR > 0) w[r].y = -w[r].y;
+      }
+    }
+    T2 v[MAXB][8];
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c) {
+      const int l = l0 + c * lstep;
+      if (l < nlines) {
+        const T2* src = buf + l * lstride;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[c][r] = src[ro[r]];
+        if (s > 0) {
+#pragma unroll
+          for (int r = 1; r < 8; ++r) v[c][r] = cmul(v[c][r], w[r]);
+        }
+        SmallDft<8, DIR, T2>::run(v[c]);
+      }
+    }
+    __syncthreads();
+    int wo[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+      wo[r] = s == 0 ? lidx<PS>(8 * i + r) : s == 1 ? lidx<PS>(8 * (i - k2) + k2 + 8 * r) : ro[r];
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c) {
+      const int l = l0 + c * lstep;
+      if (l < nlines) {
+        T2* dst = buf + l * lstride;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) dst[wo[r]] = v[c][r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int EPT, int DIR, int PS = kLdsPadShift, typename T2>
 __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
                         const T2* __restrict__ tw, int tid, int nthr) {
@@ -332,10 +400,14 @@ __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
   // keep the per-stage constants of this call from being hoisted into registers that stay live
   // across a caller's loop around the transform
   asm volatile("" : "+s"(n));
-  if (PS < kNoPad && plan.linear)
+  if (n == 512 && (nthr & 63) == 0) {
+    // nlines * 512 <= nthr * EPT, so a thread has at most ceil(EPT / 8) lines
+    lds_fft512<(EPT + 7) / 8, DIR, PS>(buf, nlines, lstride, tw, tid, nthr);
+  } else if (PS < kNoPad && plan.linear) {
     lds_fft_stages<EPT, DIR, PS, true>(buf, plan, n, nlines, lstride, tw, tid, nthr);
-  else
+  } else {
     lds_fft_stages<EPT, DIR, PS, false>(buf, plan, n, nlines, lstride, tw, tid, nthr);
+  }
 }
 
 }  // namespace vdwxc

@@ -32,8 +32,11 @@ namespace {
 // field pairs per inverse z transform in the assembly: two in FP64 (192^3: -20 % in that pass);
 // one in FP32, where the second prefetch set spills under the 128-register cap and costs
 // occupancy without it
+#ifndef VDWXC_ASM_PB64
+#define VDWXC_ASM_PB64 2
+#endif
 template <typename T>
-constexpr int asm_pb() { return sizeof(T) == 8 ? 2 : 1; }
+constexpr int asm_pb() { return sizeof(T) == 8 ? VDWXC_ASM_PB64 : 1; }
 constexpr int kEPTA = 4;         // grid points (and FFT elements) per thread in the z assembly
 constexpr int kEPT = 8;          // FFT elements per thread in the z and y passes
 #ifndef VDWXC_EPTC
@@ -52,6 +55,19 @@ constexpr int kMaxThreadsZ = 512;  // z passes
 constexpr int kMaxThreadsY = 1024; // y passes
 constexpr int kMaxThreadsX = 512;  // x passes: one thread per contraction slot
 constexpr int kLineTile = 16;    // lines per block in the z and y passes
+// Lines per block of the y passes.  Measured at 512^3: 8-line FP64 blocks (74 KB of LDS, two per
+// CU) beat 16-line ones (139 KB, one per CU) by 19 % (forward) and 28 % (inverse); in FP32 the
+// forward pass keeps 16 lines, whose transposed writes are then whole 128-byte rows (8 lines:
+// +9 %), and the inverse takes 8 (-7 %).  4-line blocks are slower in both precisions.
+#ifndef VDWXC_YTILE64
+#define VDWXC_YTILE64 8
+#endif
+#ifndef VDWXC_YTILE32
+#define VDWXC_YTILE32 16
+#endif
+#ifndef VDWXC_YTILE32_INV
+#define VDWXC_YTILE32_INV 8
+#endif
 constexpr size_t kMaxLds = 160 * 1024;
 
 thread_local std::string g_init_error;
@@ -195,7 +211,7 @@ struct vdwxc_ctx {
   int device = 0;
   Geometry geo{};
   AxisPlan plan[3]{};
-  Launch zl64, zl32, za64, za32, yl64, yl32, xl64, xl32;
+  Launch zl64, zl32, za64, za32, yl64, yl32, yl32i, xl64, xl32;
   Launch dz64, dz32, dy64, dy32, dx64, dx32;   // divergence passes (lds: the whole block)
   Launch gz, gy, gx;                           // gradient passes, FP64 (lds: the whole block)
   size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
@@ -365,8 +381,8 @@ int threads_for(long items, int ept, int maxt) {
 
 // TILE lines of length n in one block (TILE <= min(16, other)), padded stride n + 1; the LDS
 // size includes the twiddle table of the axis
-bool line_launch(int maxt, int n, int other, size_t cplx_bytes, Launch& L, int ept = kEPT) {
-  int tile = std::min(kLineTile, std::max(1, other));
+bool line_launch(int maxt, int n, int other, size_t cplx_bytes, Launch& L, int ept = kEPT, int max_tile = kLineTile) {
+  int tile = std::min(max_tile, std::max(1, other));
   while (tile > 1 && long(tile) * n > long(maxt) * ept) tile /= 2;
   if (long(tile) * n > long(maxt) * ept || n > kMaxAxis) return false;
   L.tile = tile;
@@ -679,7 +695,7 @@ struct Prec;
 template <> struct Prec<double> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl64; }
   static const Launch& za(const vdwxc_ctx* h) { return h->za64; }
-  static const Launch& y(const vdwxc_ctx* h) { return h->yl64; }
+  static const Launch& y(const vdwxc_ctx* h, int) { return h->yl64; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz64 : a == 1 ? h->dy64 : h->dx64; }
   static const double2* tw(const vdwxc_ctx* h, int a) { return h->tw[a]->d64; }
@@ -690,7 +706,7 @@ template <> struct Prec<double> {
 template <> struct Prec<float> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl32; }
   static const Launch& za(const vdwxc_ctx* h) { return h->za32; }
-  static const Launch& y(const vdwxc_ctx* h) { return h->yl32; }
+  static const Launch& y(const vdwxc_ctx* h, int dir) { return dir < 0 ? h->yl32 : h->yl32i; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz32 : a == 1 ? h->dy32 : h->dx32; }
   static const float2* tw(const vdwxc_ctx* h, int a) { return h->tw[a]->d32; }
@@ -728,7 +744,7 @@ void stage_end(vdwxc_ctx* h, const Work& w, int stage) {
 template <typename T>
 void enqueue_ypass(vdwxc_ctx* h, const Work& w, int nf, int dir, int stage) {
   using T2 = typename Cx<T>::type;
-  const Launch& L = Prec<T>::y(h);
+  const Launch& L = Prec<T>::y(h, dir);
   dim3 grid((h->n1 + L.tile - 1) / L.tile, h->h3, nf);
   T2* A = static_cast<T2*>(w.A);
   T2* B = static_cast<T2*>(w.B);
@@ -996,7 +1012,9 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
     return fail(nullptr, VDWXC_EINVAL, "grid reaches |G| >= kmax of the kernel table (grid too fine)");
   }
   bool ok = line_launch(kMaxThreadsZ, h->n3, h->n2, 16, h->zl64) && line_launch(kMaxThreadsZ, h->n3, h->n2, 8, h->zl32) &&
-            line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64) && line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32);
+            line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64, kEPT, VDWXC_YTILE64) &&
+            line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32, kEPT, VDWXC_YTILE32) &&
+            line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32i, kEPT, VDWXC_YTILE32_INV);
   {
     // contraction pass: one thread per k-point up to kMaxThreadsX (the kernel strides beyond)
     Launch& L = precision == VDWXC_FP64 ? h->xl64 : h->xl32;
@@ -1126,7 +1144,7 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_ypass<double, kEPT, -1>, h->yl64.lds);
   set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
-  set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32.lds);
+  set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32i.lds);
   set_lds_limit(k_xcontract<double, kEPTC, kXPad, 1>, h->xl64.lds);
   set_lds_limit(k_xcontract<float, kEPTC, kXPad, 1>, h->xl32.lds);
   set_lds_limit(k_xcontract<float, kEPTC, kXPad, 4>, h->xl32.lds);
