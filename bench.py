@@ -215,6 +215,9 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=40.0)
+    ap.add_argument("--density-cache", default=None,
+                    help="file holding the workload's density and gradient: read if it exists, else written "
+                         "after generating them (saves regenerating them under a profiler)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed steps, run one plain device copy of this many MiB (a "
                          "kernel of known traffic for scaling hardware byte counters)")
@@ -234,7 +237,15 @@ def main() -> int:
     w = inputs.workload(args.workload)
     say(f"workload {args.workload} grid {w.grid}, headline precision {args.precision}")
     t_in = time.perf_counter()
-    n, g = w.density(device="cuda", progress=lambda done, total: say(f"density: {done}/{total} blobs"))
+    if args.density_cache and os.path.exists(args.density_cache):
+        cached = torch.load(args.density_cache, map_location="cuda", weights_only=True)
+        if cached.get("workload") != args.workload:
+            raise SystemExit(f"{args.density_cache} holds {cached.get('workload')}, not {args.workload}")
+        n, g = cached["n"], cached["g"]
+    else:
+        n, g = w.density(device="cuda", progress=lambda done, total: say(f"density: {done}/{total} blobs"))
+        if args.density_cache:
+            torch.save({"workload": args.workload, "n": n, "g": g}, args.density_cache)
     torch.cuda.synchronize()
     say(f"density ready in {time.perf_counter() - t_in:.1f} s")
 

@@ -11,6 +11,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace vdwxc {
 
 constexpr int kMaxStages = 16;
@@ -337,15 +339,25 @@ __device__ __forceinline__ void lds_fft_stages(T2* buf, const AxisPlan& plan, in
 // so they are formed once per transform instead of once per butterfly and stage (the generic
 // stage above recomputes the line, column and k of every butterfly, then each address and the
 // twiddle index; that index arithmetic cost about as much as the butterfly itself).
-template <int MAXB, int DIR, int PS, typename T2>
+// Where the first stage takes its inputs and the last stage puts its outputs: the LDS lines
+// themselves (LdsLines), or a functor in(l, x) returning element x of line l / out(l, x, v) storing
+// it, e.g. straight from and to global memory when the lines are contiguous there.  The thread
+// handles elements x = i + 64 r of its lines in both, so 64 consecutive threads access 64
+// consecutive elements of one line.
+struct LdsLines {};
+
+template <int MAXB, int DIR, int PS, typename T2, typename In = LdsLines, typename Out = LdsLines>
 __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, const T2* __restrict__ tw, int tid,
-                                           int nthr) {
+                                           int nthr, In in = In{}, Out out = Out{}) {
+  constexpr bool kInLds = std::is_same<In, LdsLines>::value, kOutLds = std::is_same<Out, LdsLines>::value;
   int i = tid & 63;
   // the offsets and twiddles below depend on the thread alone: without this the compiler shares
   // them between the transforms of one kernel, or hoists them out of a caller's loop, and keeps
   // them live (and the caller's registers spilled) in between
   asm volatile("" : "+v"(i));
-  const int l0 = tid >> 6, lstep = nthr >> 6;
+  // a wave is 64 consecutive threads, so its line index is uniform over the wave: keep it scalar,
+  // so that line bases (in LDS and in global memory) are scalar too
+  const int l0 = __builtin_amdgcn_readfirstlane(tid >> 6), lstep = nthr >> 6;
   const int k2 = i & 7;
   int ro[8];
 #pragma unroll
@@ -361,13 +373,27 @@ __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, con
       }
     }
     T2 v[MAXB][8];
+    // all of the thread's loads first (several in flight), then the arithmetic
 #pragma unroll
     for (int c = 0; c < MAXB; ++c) {
       const int l = l0 + c * lstep;
       if (l < nlines) {
         const T2* src = buf + l * lstride;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[c][r] = src[ro[r]];
+        for (int r = 0; r < 8; ++r) {
+          if constexpr (!kInLds) {
+            if (s == 0) {
+              v[c][r] = in(l, i + 64 * r);
+              continue;
+            }
+          }
+          v[c][r] = src[ro[r]];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < MAXB; ++c) {
+      if (l0 + c * lstep < nlines) {
         if (s > 0) {
 #pragma unroll
           for (int r = 1; r < 8; ++r) v[c][r] = cmul(v[c][r], w[r]);
@@ -375,28 +401,43 @@ __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, con
         SmallDft<8, DIR, T2>::run(v[c]);
       }
     }
-    __syncthreads();
-    int wo[8];
+    if (!kOutLds && s == 2) {
+      // the last stage's outputs go straight to the caller (no LDS write, no barrier before it)
 #pragma unroll
-    for (int r = 0; r < 8; ++r)
-      wo[r] = s == 0 ? lidx<PS>(8 * i + r) : s == 1 ? lidx<PS>(8 * (i - k2) + k2 + 8 * r) : ro[r];
+      for (int c = 0; c < MAXB; ++c) {
+        const int l = l0 + c * lstep;
+        if (l < nlines) {
 #pragma unroll
-    for (int c = 0; c < MAXB; ++c) {
-      const int l = l0 + c * lstep;
-      if (l < nlines) {
-        T2* dst = buf + l * lstride;
+          for (int r = 0; r < 8; ++r) {
+            if constexpr (!kOutLds) out(l, i + 64 * r, v[c][r]);
+          }
+        }
+      }
+    } else {
+      __syncthreads();
+      int wo[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) dst[wo[r]] = v[c][r];
+      for (int r = 0; r < 8; ++r)
+        wo[r] = s == 0 ? lidx<PS>(8 * i + r) : s == 1 ? lidx<PS>(8 * (i - k2) + k2 + 8 * r) : ro[r];
+#pragma unroll
+      for (int c = 0; c < MAXB; ++c) {
+        const int l = l0 + c * lstep;
+        if (l < nlines) {
+          T2* dst = buf + l * lstride;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) dst[wo[r]] = v[c][r];
+        }
       }
     }
-    __syncthreads();
+    __syncthreads();   // (after the last stage: the caller may reuse the LDS lines)
   }
 }
 
 template <int EPT, int DIR, int PS = kLdsPadShift, typename T2>
 __device__ void lds_fft(T2* buf, const AxisPlan& plan, int nlines, int lstride,
                         const T2* __restrict__ tw, int tid, int nthr) {
-  int n = plan.n;
+  // (uniform over the block; readfirstlane keeps it scalar where the compiler lost track of that)
+  int n = __builtin_amdgcn_readfirstlane(plan.n);
   // keep the per-stage constants of this call from being hoisted into registers that stay live
   // across a caller's loop around the transform
   asm volatile("" : "+s"(n));
