@@ -340,10 +340,10 @@ __device__ __forceinline__ void lds_fft_stages(T2* buf, const AxisPlan& plan, in
 // stage above recomputes the line, column and k of every butterfly, then each address and the
 // twiddle index; that index arithmetic cost about as much as the butterfly itself).
 // Where the first stage takes its inputs and the last stage puts its outputs: the LDS lines
-// themselves (LdsLines), or a functor in(l, x) returning element x of line l / out(l, x, v) storing
-// it, e.g. straight from and to global memory when the lines are contiguous there.  The thread
-// handles elements x = i + 64 r of its lines in both, so 64 consecutive threads access 64
-// consecutive elements of one line.
+// themselves (LdsLines), or a functor in(l, r, x) returning element x = i + 64 r of line l /
+// out(l, r, x, v) storing it, e.g. straight from and to global memory when the lines are contiguous
+// there, or from and to per-point registers of the caller (r is a compile-time index: element r of
+// the thread's 8 per line).  64 consecutive threads access 64 consecutive elements of one line.
 struct LdsLines {};
 
 template <int MAXB, int DIR, int PS, typename T2, typename In = LdsLines, typename Out = LdsLines>
@@ -383,7 +383,7 @@ __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, con
         for (int r = 0; r < 8; ++r) {
           if constexpr (!kInLds) {
             if (s == 0) {
-              v[c][r] = in(l, i + 64 * r);
+              v[c][r] = in(l, r, i + 64 * r);
               continue;
             }
           }
@@ -409,7 +409,7 @@ __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, con
         if (l < nlines) {
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
-            if constexpr (!kOutLds) out(l, i + 64 * r, v[c][r]);
+            if constexpr (!kOutLds) out(l, r, i + 64 * r, v[c][r]);
           }
         }
       }

@@ -417,6 +417,110 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
   }
 }
 
+// The same pass for N3 = 512, where the transform's thread mapping fixes the points of a thread:
+// thread t owns line (y) t / 64 of the tile and the points z = t mod 64 + 64 r, r = 0..7, which
+// are exactly the inputs of its first transform stage.  So the points' q0 state stays in the
+// thread's registers from q0 to every field pair, and theta_a goes straight into the first stage:
+// no per-point state in LDS (the block holds the ty lines, the twiddles and the spline tables,
+// half the LDS of the general kernel) and no theta round trip through LDS.  nthr = 64 ty.  WPE:
+// the waves per SIMD the registers must allow (the eight points' state in FP64 needs more than
+// the 128 registers of four).
+template <typename T, bool SIGMA_FROM_GRAD, int WPE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
+                typename Cx<T>::type* __restrict__ A, Quad<T>* __restrict__ state, int* __restrict__ flag,
+                const double* __restrict__ qmesh, const double* __restrict__ mm,
+                const typename Cx<T>::type* __restrict__ tw, Geometry g, int ty, int lstride) {
+  using T2 = typename Cx<T>::type;
+  constexpr int n3 = 512;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(n3);
+  const T2* twl = stage_twiddles(smem_raw, tw, n3, threadIdx.x, blockDim.x);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  int tile, x;
+  zpass_block(tile, x);
+  const int y0 = tile * ty, M = g.M;
+  const size_t N = size_t(g.n1) * g.n2 * n3;
+  T2* line = reinterpret_cast<T2*>(smem);
+  const SplineLds<T> S = load_spline_lds<T>(smem, size_t(ty) * lstride * sizeof(T2), qmesh, mm, M, tid, nthr);
+  // the thread's points
+  const int yl = __builtin_amdgcn_readfirstlane(tid >> 6), i = tid & 63, y = y0 + yl;
+  const bool live = y < g.n2;
+  const size_t pbase = (size_t(x) * g.n2 + y) * n3 + i;
+  PointIn in[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    in[r] = PointIn{0.0, {0.0, 0.0, 0.0}};
+    if (live) in[r] = point_load(nden, sig, pbase + 64 * r, N, SIGMA_FROM_GRAD);
+  }
+  __syncthreads();   // spline tables and twiddles in LDS (the point loads are in flight meanwhile)
+  int pb[8];      // spline interval, 255: vacuum (theta = 0)
+  T pt[8], pn[8]; // position in the interval, density
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    int b = -1;
+    double t = 0.0;
+    if (live) {
+      const double sv = point_sigma(in[r], SIGMA_FROM_GRAD);
+      bad |= !(in[r].n == in[r].n) || !(sv == sv);
+      double an, as;
+      q0_state(in[r].n, sv, g.zab, S.q, M, b, t, an, as);
+      // the point's spline state for the inverse z pass: (t, n dq0/dn, n dq0/dsigma, b)
+      state[pbase + 64 * r] = Quad<T>{T(t), T(an), T(as), T(b < 0 ? 255 : b)};
+    }
+    pb[r] = b < 0 ? 255 : b;
+    pt[r] = T(t);
+    pn[r] = T(in[r].n);
+  }
+  if (bad) *flag = 1;
+
+  const int npairs = (M + 1) >> 1;
+  const size_t kzstride = size_t(g.n1) * g.n2, fstride = size_t(g.h3) * kzstride;
+#pragma unroll 1
+  for (int pr = 0; pr < npairs; ++pr) {
+    const int fa = 2 * pr, fb = 2 * pr + 1;
+    // theta_a = n p_a = n [u d_ab + t d_a,b+1 + c6 ((u^3-u) m_b,a + (t^3-t) m_b+1,a)] of fields fa,
+    // fa+1 as the real and imaginary part of the first stage's input
+    lds_fft512<1, -1, kLdsPadShift>(
+        line, ty, lstride, twl, tid, nthr,
+        [&](int, int r, int) {
+          const int b = pb[r];
+          T ta = T(0), tb = T(0);
+          if (b != 255) {
+            const T t = pt[r], nv = pn[r], u = T(1) - t;
+            const T c = S.c6[b] * nv;
+            const T wa = c * (u * u * u - u), wb = c * (t * t * t - t);
+            const T2 m0 = *reinterpret_cast<const T2*>(S.mmT + b * kMaxQ + fa);
+            const T2 m1 = *reinterpret_cast<const T2*>(S.mmT + (b + 1) * kMaxQ + fa);
+            const T nu = nv * u, nt = nv * t;
+            ta = wa * m0.x + wb * m1.x + (fa == b ? nu : T(0)) + (fa == b + 1 ? nt : T(0));
+            tb = fb < M ? wa * m0.y + wb * m1.y + (fb == b ? nu : T(0)) + (fb == b + 1 ? nt : T(0)) : T(0);
+          }
+          return T2{ta, tb};
+        },
+        LdsLines{});
+    // A[f][kz][x][y0 + yl] = Aa[kz * kzstride + yl] (field fa), Aa[fstride + ...] (field fb)
+    T2* Aa = A + a_index(g, fa, 0, x, y0);
+    const int nout = ty * g.h3;
+    DivModStep ot(tid, nthr, ty);
+#pragma unroll 1
+    for (int e = tid; e < nout; e += nthr, ot.next()) {
+      const int ol = ot.r, kz = ot.q;
+      if (y0 + ol < g.n2) {
+        const T2 zk = line[ol * lstride + lidx<>(kz)];
+        const T2 zn = line[ol * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
+        T2 xa, xb;
+        split_pair(zk, zn, xa, xb);
+        T2* dst = Aa + size_t(kz) * kzstride + ol;
+        dst[0] = xa;
+        if (fb < M) dst[fstride] = xb;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---- pass 2 / 4: y FFT with rotation A[f][kz][x][y] <-> B[f][ky][kz][x] ----------------------
 // Block: TX consecutive x of one (f, kz) (blockIdx.x = x tile, .y = kz, .z = f).
 
@@ -441,7 +545,8 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     const T2* sbase = src + a_index(g, f, kz, x0, 0);
     lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift>(
         line, tx, lstride, twl, tid, nthr,
-        [&](int xl, int y) { return (x0 + xl < g.n1) ? sbase[size_t(xl) * 512 + y] : T2{T(0), T(0)}; }, LdsLines{});
+        [&](int xl, int, int y) { return (x0 + xl < g.n1) ? sbase[size_t(xl) * 512 + y] : T2{T(0), T(0)}; },
+        LdsLines{});
   } else if (DIR < 0) {
     const T2* sbase = src + a_index(g, f, kz, x0, 0);
     gather_strided_dm<8>(
@@ -460,7 +565,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     __syncthreads();
     T2* dbase = dst + a_index(g, f, kz, x0, 0);
     lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift>(line, tx, lstride, twl, tid, nthr, LdsLines{},
-                                                [&](int xl, int y, T2 v) {
+                                                [&](int xl, int, int y, T2 v) {
                                                   if (x0 + xl < g.n1) dbase[size_t(xl) * 512 + y] = v;
                                                 });
     return;
@@ -597,7 +702,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
   const bool f512 = n1 == 512 && (nthr & 63) == 0 && M <= G;
   if (f512) {
     lds_fft512<(EPT + 7) / 8, -1, PS>(line, M, ls, twl, tid, nthr,
-                                      [&](int f, int x) { return cb[size_t(f) * fstride + x]; }, LdsLines{});
+                                      [&](int f, int, int x) { return cb[size_t(f) * fstride + x]; }, LdsLines{});
   } else {
     gather_strided_dm<16>(
         tid, nthr, M * n1, n1, [&](int, int f, int x) { return cb[size_t(f) * fstride + x]; },

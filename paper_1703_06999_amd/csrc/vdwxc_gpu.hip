@@ -32,6 +32,19 @@ namespace {
 // field pairs per inverse z transform in the assembly: two in FP64 (192^3: -20 % in that pass);
 // one in FP32, where the second prefetch set spills under the 128-register cap and costs
 // occupancy without it
+// the register-state theta pass for N3 = 512 (k_theta_zfwd512): lines per block and waves per
+// SIMD its registers allow, per precision
+#ifndef VDWXC_T512_TILE64
+#define VDWXC_T512_TILE64 8
+#endif
+#ifndef VDWXC_T512_WPE64
+#define VDWXC_T512_WPE64 2
+#endif
+#ifndef VDWXC_T512_TILE32
+#define VDWXC_T512_TILE32 8
+#endif
+template <typename T>
+constexpr int t512_wpe() { return sizeof(T) == 8 ? VDWXC_T512_WPE64 : 4; }
 #ifndef VDWXC_ASM_PB64
 #define VDWXC_ASM_PB64 2
 #endif
@@ -216,6 +229,8 @@ struct vdwxc_ctx {
   Launch gz, gy, gx;                           // gradient passes, FP64 (lds: the whole block)
   size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
   bool x_capped = false;   // launch the register-capped contraction kernel
+  bool z512 = false;       // N3 = 512: the register-state theta pass
+  Launch t512_64, t512_32; // its launch (lds: the whole block)
   bool ortho = false;
   // shared read-only device tables (reference counted, see TableEntry / TwiddleEntry)
   TableEntry* tab = nullptr;
@@ -695,6 +710,7 @@ struct Prec;
 template <> struct Prec<double> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl64; }
   static const Launch& za(const vdwxc_ctx* h) { return h->za64; }
+  static const Launch& z512(const vdwxc_ctx* h) { return h->t512_64; }
   static const Launch& y(const vdwxc_ctx* h, int) { return h->yl64; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz64 : a == 1 ? h->dy64 : h->dx64; }
@@ -706,6 +722,7 @@ template <> struct Prec<double> {
 template <> struct Prec<float> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl32; }
   static const Launch& za(const vdwxc_ctx* h) { return h->za32; }
+  static const Launch& z512(const vdwxc_ctx* h) { return h->t512_32; }
   static const Launch& y(const vdwxc_ctx* h, int dir) { return dir < 0 ? h->yl32 : h->yl32i; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz32 : a == 1 ? h->dy32 : h->dx32; }
@@ -816,12 +833,23 @@ void enqueue_main(vdwxc_ctx* h, const Work& w, const double* n, const double* si
   stage_begin(h, w);
   const size_t lds_theta = Prec<T>::theta_lds(h), lds_asm = Prec<T>::asm_lds(h);
   Quad<T>* state = static_cast<Quad<T>*>(w.state);
-  if (sig_from_grad)
+  if (h->z512) {
+    // N3 = 512: the register-state theta pass (k_theta_zfwd512), 64 threads per line
+    const Launch& L5 = Prec<T>::z512(h);
+    const dim3 g5((h->n2 + L5.tile - 1) / L5.tile, h->n1);
+    if (sig_from_grad)
+      hipLaunchKernelGGL((k_theta_zfwd512<T, true, t512_wpe<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.flag,
+                         tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride);
+    else
+      hipLaunchKernelGGL((k_theta_zfwd512<T, false, t512_wpe<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.flag,
+                         tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride);
+  } else if (sig_from_grad) {
     hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, true>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A, state,
                        w.flag, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
-  else
+  } else {
     hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, false>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A, state,
                        w.flag, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], Lz.tile, Lz.lstride);
+  }
   stage_end(h, w, VDWXC_STAGE_THETA_ZFWD);
   enqueue_ypass<T>(h, w, h->M, -1, VDWXC_STAGE_Y_FWD);
   stage_begin(h, w);
@@ -1132,6 +1160,24 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
       release(h);
       return fail(nullptr, VDWXC_EINVAL, "grid too large for one block per line (see size limits in vdwxc_gpu.h)");
     }
+  }
+
+  // N3 = 512: the register-state theta pass takes 64 threads per line and VDWXC_T512_TILE* lines
+  // per block (fewer when N2 is smaller); its LDS is the lines, the twiddles and the spline tables
+  h->z512 = h->n3 == 512;
+  if (h->z512) {
+    for (Launch* L : {&h->t512_64, &h->t512_32}) {
+      const size_t cplx = L == &h->t512_64 ? 16 : 8;
+      L->tile = std::min(cplx == 16 ? VDWXC_T512_TILE64 : VDWXC_T512_TILE32, h->n2);
+      L->nthr = 64 * L->tile;
+      L->lstride = lds_span<>(512);
+      L->lds = tw_lds_bytes<double2>(512) * cplx / 16 + size_t(L->tile) * L->lstride * cplx +
+               (cplx == 16 ? spline_lds_bytes<double>() : spline_lds_bytes<float>()) + 16;
+    }
+    set_lds_limit(k_theta_zfwd512<double, true, t512_wpe<double>()>, h->t512_64.lds);
+    set_lds_limit(k_theta_zfwd512<double, false, t512_wpe<double>()>, h->t512_64.lds);
+    set_lds_limit(k_theta_zfwd512<float, true, t512_wpe<float>()>, h->t512_32.lds);
+    set_lds_limit(k_theta_zfwd512<float, false, t512_wpe<float>()>, h->t512_32.lds);
   }
 
   // dynamic LDS above the default limit
