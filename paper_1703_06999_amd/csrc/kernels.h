@@ -1087,6 +1087,126 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __res
   }
 }
 
+// The same pass for N3 = 512 (the counterpart of k_theta_zfwd512): thread t owns line (y) t / 64
+// of the tile and the points z = t mod 64 + 64 r, which are exactly the outputs of its last
+// inverse-transform stage.  Their spline state stays in registers, and the two spline sums of each
+// point accumulate straight from that stage (no per-point state in LDS, no read of the transformed
+// lines).  Field pairs go through the transform PB at a time; with PREFETCH the next batch's half
+// spectra are in flight during the transform (more registers), else they are loaded after it.
+// nthr = 64 ty.
+template <typename T, int PB, int WPE, bool PREFETCH>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_zinv_assemble512(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __restrict__ state,
+                   double* __restrict__ dedn, double* __restrict__ dedsig, const double* __restrict__ qmesh,
+                   const double* __restrict__ mm, const typename Cx<T>::type* __restrict__ tw, Geometry g, int ty,
+                   int lstride, const double* __restrict__ partials, int nparts, double escale,
+                   int* __restrict__ flag, double* __restrict__ energy) {
+  using T2 = typename Cx<T>::type;
+  constexpr int n3 = 512;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned char* smem = smem_raw + tw_lds_bytes<T2>(n3);
+  const T2* twl = stage_twiddles(smem_raw, tw, n3, threadIdx.x, blockDim.x);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  // the energy of the evaluation (the contraction pass left its partials), in the first block,
+  // with the line area of LDS as scratch before anything else uses it
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    energy_reduce_block(partials, nparts, escale, flag, energy, reinterpret_cast<double*>(smem), tid, nthr);
+  int tile, x;
+  zpass_block(tile, x);
+  const int y0 = tile * ty, M = g.M;
+  const size_t N = size_t(g.n1) * g.n2 * n3;
+  T2* line = reinterpret_cast<T2*>(smem);   // PB line sets of ty lines
+  const SplineLds<T> S = load_spline_lds<T>(smem, size_t(PB) * ty * lstride * sizeof(T2), qmesh, mm, M, tid, nthr);
+  const int yl = __builtin_amdgcn_readfirstlane(tid >> 6), i = tid & 63, y = y0 + yl;
+  const bool live = y < g.n2;
+  const size_t pbase = (size_t(x) * g.n2 + y) * n3 + i;
+  // the spline state of the thread's points, as the forward theta pass left it
+  int pb[8];
+  T pt[8], pan[8], pas[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    Quad<T> q{T(0), T(0), T(0), T(255)};
+    if (live) q = state[pbase + 64 * r];
+    pb[r] = int(q.w);
+    pt[r] = q.x;
+    pan[r] = q.y;
+    pas[r] = q.z;
+  }
+  // Per point, with F_a the inverse transforms and m_c,a = p_a''(q_c):
+  //   sum_a F_a p_a  = u F_b + t F_b+1 + c6 [(u^3-u) X0 + (t^3-t) X1]
+  //   sum_a F_a p_a' = (F_b+1 - F_b)/h + (h/6) [-(3u^2-1) X0 + (3t^2-1) X1]
+  // with X0 = sum_a F_a m_b,a, X1 = sum_a F_a m_b+1,a (u = 1-t), as in k_zinv_assemble.
+  double X0[8], X1[8];
+  T Fb[8], Fb1[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    X0[r] = X1[r] = 0.0;
+    Fb[r] = Fb1[r] = T(0);
+  }
+  const int npairs = (M + 1) >> 1;
+  PairPrefetch<T2, 5> pf[PB];   // ceil(ty * 257 / (64 ty)) = 5 half-spectrum values per field and thread
+#pragma unroll
+  for (int q = 0; q < PB; ++q)
+    if (q < npairs) pf[q].issue(A, g, 2 * q, 2 * q + 1 < M ? 2 * q + 1 : -1, x, y0, ty, tid, nthr);
+#pragma unroll 1
+  for (int pr0 = 0; pr0 < npairs; pr0 += PB) {
+    const int nb = min(PB, npairs - pr0);
+    if (!PREFETCH && pr0 > 0) {
+#pragma unroll
+      for (int q = 0; q < PB; ++q)
+        if (pr0 + q < npairs)
+          pf[q].issue(A, g, 2 * (pr0 + q), 2 * (pr0 + q) + 1 < M ? 2 * (pr0 + q) + 1 : -1, x, y0, ty, tid, nthr);
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      if (q < nb) pf[q].store(g, ty, line + q * ty * lstride, lstride, tid, nthr);
+    __syncthreads();
+    if (PREFETCH) {
+#pragma unroll
+      for (int q = 0; q < PB; ++q) {
+        const int pn = pr0 + PB + q;
+        if (pn < npairs) pf[q].issue(A, g, 2 * pn, 2 * pn + 1 < M ? 2 * pn + 1 : -1, x, y0, ty, tid, nthr);
+      }
+    }
+    lds_fft512<PB, +1, kLdsPadShift>(
+        line, nb * ty, lstride, twl, tid, nthr, LdsLines{}, [&](int l, int r, int, T2 F) {
+          const int fa = 2 * (pr0 + (l - yl) / ty), fb = fa + 1 < M ? fa + 1 : -1;
+          const int b = pb[r];
+          if (b != 255) {
+            // m entries of fields fa, fa+1 at knots b and b+1 (adjacent in the transposed table)
+            const T2 m0 = *reinterpret_cast<const T2*>(S.mmT + b * kMaxQ + fa);
+            const T2 m1 = *reinterpret_cast<const T2*>(S.mmT + (b + 1) * kMaxQ + fa);
+            const T m0y = fb >= 0 ? m0.y : T(0), m1y = fb >= 0 ? m1.y : T(0);
+            X0[r] += double(F.x * m0.x + F.y * m0y);
+            X1[r] += double(F.x * m1.x + F.y * m1y);
+            if (fa == b) Fb[r] = F.x;
+            if (fb == b) Fb[r] = F.y;
+            if (fa == b + 1) Fb1[r] = F.x;
+            if (fb == b + 1) Fb1[r] = F.y;
+          }
+        });
+  }
+  if (live) {
+    const double invN = 1.0 / double(N);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      double vn = 0.0, vs = 0.0;
+      const int b = pb[r];
+      if (b != 255) {
+        const double t = pt[r], an = pan[r], as = pas[r];
+        const double hh = S.h[b], c6 = S.c6[b], u = 1.0 - t;
+        const double fb0 = Fb[r], fb1 = Fb1[r];
+        const double P = u * fb0 + t * fb1 + c6 * ((u * u * u - u) * X0[r] + (t * t * t - t) * X1[r]);
+        const double D = (fb1 - fb0) / hh + hh * (1.0 / 6.0) * (-(3.0 * u * u - 1.0) * X0[r] + (3.0 * t * t - 1.0) * X1[r]);
+        vn = P + an * D;
+        vs = as * D;
+      }
+      dedn[pbase + 64 * r] = vn * invN;
+      dedsig[pbase + 64 * r] = vs * invN;
+    }
+  }
+}
+
 // ---- spectral divergence, one axis at a time ---------------------------------------------------
 // The divergence of h_c = 2 (dE/dsigma) g_c is (1/N) F^-1 [chi(m) sum_c i G_c F h_c] with G the
 // wave vector of index m and chi zero wherever an index is a Nyquist index.  With G = sum_i m_i b_i

@@ -45,6 +45,44 @@ namespace {
 #endif
 template <typename T>
 constexpr int t512_wpe() { return sizeof(T) == 8 ? VDWXC_T512_WPE64 : 4; }
+// the register-state assembly for N3 = 512 (k_zinv_assemble512): lines per block, field pairs per
+// transform and waves per SIMD, per precision
+#ifndef VDWXC_A512_TILE64
+#define VDWXC_A512_TILE64 8
+#endif
+#ifndef VDWXC_A512_PB64
+#define VDWXC_A512_PB64 1
+#endif
+#ifndef VDWXC_A512_WPE64
+#define VDWXC_A512_WPE64 2
+#endif
+#ifndef VDWXC_A512_TILE32
+#define VDWXC_A512_TILE32 8
+#endif
+template <typename T>
+constexpr int a512_pb() { return sizeof(T) == 8 ? VDWXC_A512_PB64 : 1; }
+#ifndef VDWXC_A512_WPE32
+#define VDWXC_A512_WPE32 4
+#endif
+// Measured at 512^3: FP64 14.3 -> 12.6 ms (8-line blocks, no prefetch; prefetching the next pair
+// measured 12.9); in FP32 the register-state version loses to the general kernel (7.9 ms against
+// 11.7 with 8-line blocks at four waves per SIMD, 9.5 with 4-line blocks at three), so FP32 keeps
+// k_zinv_assemble.
+#ifndef VDWXC_A512_FP32
+#define VDWXC_A512_FP32 0
+#endif
+template <typename T>
+constexpr bool a512_used() { return sizeof(T) == 8 ? true : VDWXC_A512_FP32; }
+template <typename T>
+constexpr int a512_wpe() { return sizeof(T) == 8 ? VDWXC_A512_WPE64 : VDWXC_A512_WPE32; }
+#ifndef VDWXC_A512_PF64
+#define VDWXC_A512_PF64 0
+#endif
+#ifndef VDWXC_A512_PF32
+#define VDWXC_A512_PF32 0
+#endif
+template <typename T>
+constexpr bool a512_pf() { return sizeof(T) == 8 ? VDWXC_A512_PF64 : VDWXC_A512_PF32; }
 #ifndef VDWXC_ASM_PB64
 #define VDWXC_ASM_PB64 2
 #endif
@@ -231,6 +269,7 @@ struct vdwxc_ctx {
   bool x_capped = false;   // launch the register-capped contraction kernel
   bool z512 = false;       // N3 = 512: the register-state theta pass
   Launch t512_64, t512_32; // its launch (lds: the whole block)
+  Launch a512_64, a512_32; // the register-state assembly for N3 = 512
   bool ortho = false;
   // shared read-only device tables (reference counted, see TableEntry / TwiddleEntry)
   TableEntry* tab = nullptr;
@@ -711,6 +750,7 @@ template <> struct Prec<double> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl64; }
   static const Launch& za(const vdwxc_ctx* h) { return h->za64; }
   static const Launch& z512(const vdwxc_ctx* h) { return h->t512_64; }
+  static const Launch& a512(const vdwxc_ctx* h) { return h->a512_64; }
   static const Launch& y(const vdwxc_ctx* h, int) { return h->yl64; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz64 : a == 1 ? h->dy64 : h->dx64; }
@@ -723,6 +763,7 @@ template <> struct Prec<float> {
   static const Launch& z(const vdwxc_ctx* h) { return h->zl32; }
   static const Launch& za(const vdwxc_ctx* h) { return h->za32; }
   static const Launch& z512(const vdwxc_ctx* h) { return h->t512_32; }
+  static const Launch& a512(const vdwxc_ctx* h) { return h->a512_32; }
   static const Launch& y(const vdwxc_ctx* h, int dir) { return dir < 0 ? h->yl32 : h->yl32i; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl32; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz32 : a == 1 ? h->dy32 : h->dx32; }
@@ -870,9 +911,18 @@ void enqueue_main(vdwxc_ctx* h, const Work& w, const double* n, const double* si
   const Launch& La = Prec<T>::za(h);
   const dim3 agrid((h->n2 + La.tile - 1) / La.tile, h->n1);
   const double N = double(h->n1) * h->n2 * h->n3;
-  hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, asm_pb<T>()>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state, dedn,
-                     dedsig, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile, La.lstride,
-                     w.partials, h->n2 * h->h3, h->omega / (2.0 * N * N), w.flag, energy, La.sets);
+  if (h->z512 && a512_used<T>()) {
+    // N3 = 512: the register-state assembly (k_zinv_assemble512), 64 threads per line
+    const Launch& L5 = Prec<T>::a512(h);
+    const dim3 g5((h->n2 + L5.tile - 1) / L5.tile, h->n1);
+    hipLaunchKernelGGL((k_zinv_assemble512<T, a512_pb<T>(), a512_wpe<T>(), a512_pf<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, A,
+                       state, dedn, dedsig, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride, w.partials,
+                       h->n2 * h->h3, h->omega / (2.0 * N * N), w.flag, energy);
+  } else {
+    hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, asm_pb<T>()>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state,
+                       dedn, dedsig, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, h->plan[2], La.tile, La.lstride,
+                       w.partials, h->n2 * h->h3, h->omega / (2.0 * N * N), w.flag, energy, La.sets);
+  }
   stage_end(h, w, VDWXC_STAGE_Z_ASSEMBLE);
 }
 
@@ -1174,6 +1224,19 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
       L->lds = tw_lds_bytes<double2>(512) * cplx / 16 + size_t(L->tile) * L->lstride * cplx +
                (cplx == 16 ? spline_lds_bytes<double>() : spline_lds_bytes<float>()) + 16;
     }
+    for (Launch* L : {&h->a512_64, &h->a512_32}) {
+      const size_t cplx = L == &h->a512_64 ? 16 : 8;
+      const int pb = cplx == 16 ? a512_pb<double>() : a512_pb<float>();
+      L->tile = std::min(cplx == 16 ? VDWXC_A512_TILE64 : VDWXC_A512_TILE32, h->n2);
+      L->nthr = 64 * L->tile;
+      L->lstride = lds_span<>(512);
+      L->lds = std::max(tw_lds_bytes<double2>(512) * cplx / 16 + size_t(pb) * L->tile * L->lstride * cplx +
+                            (cplx == 16 ? spline_lds_bytes<double>() : spline_lds_bytes<float>()) + 16,
+                        // the first block's energy sum uses one double per wave of LDS
+                        tw_lds_bytes<double2>(512) * cplx / 16 + size_t(L->nthr / 64) * sizeof(double));
+    }
+    set_lds_limit(k_zinv_assemble512<double, a512_pb<double>(), a512_wpe<double>(), a512_pf<double>()>, h->a512_64.lds);
+    set_lds_limit(k_zinv_assemble512<float, a512_pb<float>(), a512_wpe<float>(), a512_pf<float>()>, h->a512_32.lds);
     set_lds_limit(k_theta_zfwd512<double, true, t512_wpe<double>()>, h->t512_64.lds);
     set_lds_limit(k_theta_zfwd512<double, false, t512_wpe<double>()>, h->t512_64.lds);
     set_lds_limit(k_theta_zfwd512<float, true, t512_wpe<float>()>, h->t512_32.lds);
