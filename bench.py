@@ -128,7 +128,7 @@ def cpu_baseline(workload_name: str, n_cpu, g_cpu, w, kt):
             "workload": workload_name, "seconds": round(dt, 3), "stage_seconds": stages, **host}
 
 
-def time_form(f, n, g, steps: int, warmup: int, grid, precision: str):
+def time_form(f, n, g, steps: int, warmup: int, grid, precision: str, m: int = M):
     """Warm up, then time `steps` evaluations twice (plain, then with per-kernel HIP events).
     Returns (ms_per_step, stages, roofline, v, E)."""
     import torch
@@ -157,15 +157,15 @@ def time_form(f, n, g, steps: int, warmup: int, grid, precision: str):
     f.enable_timing(False)
     ms_per_step = 1e3 * (t1 - t0) / steps
     per_stage = {k: {"ms_avg": round(ms / cnt, 4), "launches": cnt,
-                     "GBps": round(stage_bytes(k, grid, precision) / (ms / cnt * 1e-3) / 1e9, 1),
-                     "frac_hbm": round(stage_bytes(k, grid, precision) / (ms / cnt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                     "GBps": round(stage_bytes(k, grid, precision, m) / (ms / cnt * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(stage_bytes(k, grid, precision, m) / (ms / cnt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                  for k, (ms, cnt) in stages.items()}
     dom = max(stages, key=lambda k: stages[k][0])
     avg_s = stages[dom][0] / stages[dom][1] * 1e-3
-    achieved = stage_bytes(dom, grid, precision) / avg_s / 1e9
+    achieved = stage_bytes(dom, grid, precision, m) / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": stage_bytes(dom, grid, precision),
+                "algorithmic_bytes_per_launch": stage_bytes(dom, grid, precision, m),
                 "avg_launch_ms": round(avg_s * 1e3, 4),
                 "timing": "HIP events around each kernel over a second timed region of the same steps "
                           f"({1e3 * (t3 - t2) / steps:.4f} ms/step with the events)"}
@@ -213,6 +213,8 @@ def main() -> int:
     ap.add_argument("--cpu-workload", default="slater_128",
                     help="workload of the oracle timing (the 512^3 workload is beyond a bounded host run)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-qmesh", action="store_true",
+                    help="skip the timing of the headline form with a 10-point q-mesh")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--density-cache", default=None,
@@ -262,6 +264,24 @@ def main() -> int:
         if prec == args.precision:
             torch.cuda.synchronize()
         del f
+    qmesh = None
+    if not args.no_qmesh:
+        # the same workload and form with a 10-point q-mesh: the FFT passes scale with M, the
+        # contraction with its pair count M(M+1)/2 (bucket 10: 55 pairs against 210)
+        m10 = 10
+        kt10 = inputs.synthetic_kernel_table(qmesh=inputs.log_qmesh(m10))
+        f = vdwxc.Functional(w.grid, w.cell, flavour="DF1", precision=args.precision, table=kt10)
+        steps10 = max(2, args.steps // 2)
+        ms10, st10, _, v10, E10 = time_form(f, n, g, steps10, max(1, args.warmup // 2), w.grid, args.precision, m10)
+        f.close()
+        del f, v10
+        x20 = results[args.precision]["stages"]["x_contract"]["ms_avg"]
+        qmesh = {"n_alpha": m10, "steps": steps10, "ms_per_step": round(ms10, 4),
+                 "ms_per_step_n_alpha_20": round(results[args.precision]["ms"], 4),
+                 "x_contract_ms": st10["x_contract"]["ms_avg"], "x_contract_ms_n_alpha_20": x20,
+                 "x_contract_ratio": round(st10["x_contract"]["ms_avg"] / x20, 4),
+                 "stages": st10}
+        say(f"q-mesh {m10}: {ms10:.3f} ms/step, x_contract {st10['x_contract']['ms_avg']:.3f} ms (M=20: {x20:.3f})")
     if args.copy_calibration_mb:
         # one streaming elementwise kernel (negation) reading and writing N bytes each
         nel = args.copy_calibration_mb * (1 << 20) // 8
@@ -334,6 +354,7 @@ def main() -> int:
         "stages": head["stages"],
         "fp32_mixed" if prec == "fp64" else "fp64": second,
         "serving": serve,
+        "q_mesh_10": qmesh,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -643,10 +643,9 @@ struct PairList {
 };
 constexpr PairList kPairs{};
 
-// load chunks of the contraction that hold a pair of an M-point q-mesh
-__host__ __device__ constexpr int used_chunks(int M, int chunk) {
-  return ((M * (M + 1) / 2 + 1) / 2 + chunk - 1) / chunk;
-}
+// q-mesh buckets of the contraction kernel (its MB parameter): the smallest of 8, 10, 12, 16, 20
+// that holds M
+__host__ __device__ constexpr int q_bucket(int M) { return M <= 8 ? 8 : M <= 10 ? 10 : M <= 12 ? 12 : M <= 16 ? 16 : 20; }
 
 #ifndef VDWXC_XCHUNK
 #define VDWXC_XCHUNK 3
@@ -681,7 +680,11 @@ __device__ __forceinline__ void static_for(Body&& body) {
 // twiddles read from global memory, the 20 FP32 lines of a 512-point axis take exactly 80 KB, so
 // two blocks can share a CU; WPE = 4 caps the registers at 128 so that two 512-thread blocks also
 // fit the register file (the launch picks it for such blocks).
-template <typename T, int EPT, int PS, int WPE>
+// MB: the q-mesh bucket, M <= MB (one of q_bucket's values).  The per-thread field arrays, the
+// pair list and the table chunks the kernel reads are those of an MB-point mesh: the pairs (a, b)
+// with b < MB are the first MB(MB+1)/2 (pair_index order), so a shorter mesh contracts and loads
+// in proportion to MB(MB+1)/2.
+template <typename T, int EPT, int PS, int WPE, int MB>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ table4,
             double* __restrict__ partials, const typename Cx<T>::type* __restrict__ tw,
@@ -733,11 +736,11 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
       kx[0] = x;
       valid[0] = true;
     }
-    T2 th[NPT][kMaxQ], F[NPT][kMaxQ];
+    T2 th[NPT][MB], F[NPT][MB];
 #pragma unroll
     for (int q = 0; q < NPT; ++q)
 #pragma unroll
-      for (int a = 0; a < kMaxQ; ++a) {
+      for (int a = 0; a < MB; ++a) {
         th[q][a] = (a < M && valid[q]) ? line[a * ls + lidx<PS>(kx[q])] : T2{T(0), T(0)};
         F[q][a] = T2{T(0), T(0)};
       }
@@ -746,7 +749,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     const bool inside = kn < g.kmax;
     if (!inside) {
 #pragma unroll
-      for (int a = 0; a < kMaxQ; ++a) th[0][a] = T2{T(0), T(0)};
+      for (int a = 0; a < MB; ++a) th[0][a] = T2{T(0), T(0)};
     }
     const double sc = kn * g.inv_dk;
     int j = inside ? int(floor(sc)) : 0;
@@ -761,7 +764,8 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     // chunk offsets are formed up front and stay live).  Each pair is read and interpolated once
     // (phi is symmetric) and feeds F_a += phi theta_b and F_b += phi theta_a.  The next chunk's
     // loads are issued before the current chunk's arithmetic.
-    constexpr int kGroups = kNumPairs / 2;
+    constexpr int kPairsMB = MB * (MB + 1) / 2;
+    constexpr int kGroups = (kPairsMB + 1) / 2;
     constexpr int kChunks = (kGroups + kXChunk - 1) / kXChunk;
     constexpr int kQ = int(sizeof(Quad<T>));
     const int joff = j * (kXChunk * kQ);
@@ -798,11 +802,13 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
               F[q][b0].x += phi0 * th[q][a0].x;
               F[q][b0].y += phi0 * th[q][a0].y;
             }
-            F[q][a1].x += phi1 * th[q][b1].x;
-            F[q][a1].y += phi1 * th[q][b1].y;
-            if (a1 != b1) {
-              F[q][b1].x += phi1 * th[q][a1].x;
-              F[q][b1].y += phi1 * th[q][a1].y;
+            if (2 * grp + 1 < kPairsMB) {   // an odd pair count leaves the last entry half used
+              F[q][a1].x += phi1 * th[q][b1].x;
+              F[q][a1].y += phi1 * th[q][b1].y;
+              if (a1 != b1) {
+                F[q][b1].x += phi1 * th[q][a1].x;
+                F[q][b1].y += phi1 * th[q][a1].y;
+              }
             }
           }
         }
@@ -812,14 +818,14 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
 #pragma unroll
       for (int q = 0; q < NPT; ++q)
 #pragma unroll
-        for (int a = 0; a < kMaxQ; ++a) asm volatile("" : "+v"(F[q][a].x), "+v"(F[q][a].y));
+        for (int a = 0; a < MB; ++a) asm volatile("" : "+v"(F[q][a].x), "+v"(F[q][a].y));
     }
 #undef VDWXC_TLOAD_CHUNK
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
       if (valid[q]) {
 #pragma unroll
-        for (int a = 0; a < kMaxQ; ++a) {
+        for (int a = 0; a < MB; ++a) {
           if (a < M) {
             e += double(th[q][a].x) * double(F[q][a].x) + double(th[q][a].y) * double(F[q][a].y);
             line[a * ls + lidx<PS>(kx[q])] = F[q][a];

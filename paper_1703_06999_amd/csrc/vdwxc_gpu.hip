@@ -859,6 +859,27 @@ void enqueue_divergence(vdwxc_ctx* h, const Work& w, const double* S, const doub
   stage_end(h, w, VDWXC_STAGE_DIV_X);
 }
 
+// the contraction pass for q-mesh bucket MB (FP32: the register-capped kernel where chosen)
+template <typename T, int MB>
+void launch_xcontract(vdwxc_ctx* h, const Work& w, typename Cx<T>::type* B) {
+  const Launch& Lx = Prec<T>::x(h);
+  if constexpr (sizeof(T) == 4) {
+    if (h->x_capped) {
+      hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 4, MB>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream,
+                         B, Prec<T>::table(h), w.partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 1, MB>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
+                     Prec<T>::table(h), w.partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
+}
+
+template <typename T, int MB>
+void set_xcontract_lds(size_t lds) {
+  set_lds_limit(k_xcontract<T, kEPTC, kXPad, 1, MB>, lds);
+  if constexpr (sizeof(T) == 4) set_lds_limit(k_xcontract<T, kEPTC, kXPad, 4, MB>, lds);
+}
+
 // the five steps: theta + z FFT, y FFT, x FFT + contraction + inverse x, inverse y, inverse z +
 // derivatives; then the energy sum
 template <typename T>
@@ -894,17 +915,13 @@ void enqueue_main(vdwxc_ctx* h, const Work& w, const double* n, const double* si
   stage_end(h, w, VDWXC_STAGE_THETA_ZFWD);
   enqueue_ypass<T>(h, w, h->M, -1, VDWXC_STAGE_Y_FWD);
   stage_begin(h, w);
-  bool launched = false;
-  if constexpr (sizeof(T) == 4) {
-    if (h->x_capped) {
-      hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 4>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream,
-                         B, Prec<T>::table(h), w.partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
-      launched = true;
-    }
+  switch (q_bucket(h->M)) {
+    case 8: launch_xcontract<T, 8>(h, w, B); break;
+    case 10: launch_xcontract<T, 10>(h, w, B); break;
+    case 12: launch_xcontract<T, 12>(h, w, B); break;
+    case 16: launch_xcontract<T, 16>(h, w, B); break;
+    default: launch_xcontract<T, 20>(h, w, B); break;
   }
-  if (!launched)
-    hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 1>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
-                       Prec<T>::table(h), w.partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
   stage_end(h, w, VDWXC_STAGE_X_CONTRACT);
   enqueue_ypass<T>(h, w, h->M, +1, VDWXC_STAGE_Y_INV);
   stage_begin(h, w);
@@ -1254,9 +1271,13 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
   set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32i.lds);
-  set_lds_limit(k_xcontract<double, kEPTC, kXPad, 1>, h->xl64.lds);
-  set_lds_limit(k_xcontract<float, kEPTC, kXPad, 1>, h->xl32.lds);
-  set_lds_limit(k_xcontract<float, kEPTC, kXPad, 4>, h->xl32.lds);
+  switch (q_bucket(nq)) {
+    case 8: set_xcontract_lds<double, 8>(h->xl64.lds); set_xcontract_lds<float, 8>(h->xl32.lds); break;
+    case 10: set_xcontract_lds<double, 10>(h->xl64.lds); set_xcontract_lds<float, 10>(h->xl32.lds); break;
+    case 12: set_xcontract_lds<double, 12>(h->xl64.lds); set_xcontract_lds<float, 12>(h->xl32.lds); break;
+    case 16: set_xcontract_lds<double, 16>(h->xl64.lds); set_xcontract_lds<float, 16>(h->xl32.lds); break;
+    default: set_xcontract_lds<double, 20>(h->xl64.lds); set_xcontract_lds<float, 20>(h->xl32.lds); break;
+  }
   set_lds_limit(k_grad_z<double, kEPT>, h->gz.lds);
   set_lds_limit(k_grad_y<double, kEPT>, h->gy.lds);
   set_lds_limit(k_grad_x<double, kEPT>, h->gx.lds);

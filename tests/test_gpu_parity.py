@@ -178,15 +178,29 @@ def test_maximum_axis_lengths(dev, precision, grid):
     close_fields(v.cpu(), v_ref, tol["f"], "v", n, tol["wl1"])
 
 
+# q-mesh sizes and the contraction bucket (8, 10, 12, 16, 20) each falls in; the 512-point x
+# lines take the contraction's direct-load path
+Q_MESHES = [
+    (7, (24, 18, 30), 7.0),
+    (12, (24, 18, 30), 7.0),
+    (4, (24, 18, 30), 7.0),
+    (9, (24, 18, 30), 7.0),    # bucket 10, whose 55 pairs leave the last table entry half used
+    (10, (24, 18, 30), 7.0),
+    (13, (24, 18, 30), 7.0),
+    (16, (24, 18, 30), 7.0),
+    (10, (512, 6, 10), 80.0),
+    (16, (512, 6, 10), 80.0),
+]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("m", [7, 12, 4])
-def test_smaller_q_meshes(dev, precision, m):
+@pytest.mark.parametrize("m,grid,L", Q_MESHES)
+def test_smaller_q_meshes(dev, precision, m, grid, L):
     """q-meshes shorter than 20 points (4 is the smallest the library takes), odd and even: the
-    last field unpaired in the z passes, and kernel-table pairs beyond the mesh empty in the
-    contraction."""
-    say(f"[q-mesh M={m}] {precision}")
+    last field unpaired in the z passes, and the contraction reading only the pairs of its
+    q-mesh bucket."""
+    say(f"[q-mesh M={m}] {grid} {precision}")
     kt = inputs.synthetic_kernel_table(qmesh=inputs.log_qmesh(m))
-    grid, L = (24, 18, 30), 7.0
     n, g, sigma = ragged_case(grid, L, 40 + m, floor=1e-4)
     cell = inputs.cubic_cell(L)
     from paper_1703_06999_amd import vdwxc
