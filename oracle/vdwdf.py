@@ -18,6 +18,8 @@ Steps (Sec. 3, Table 1, and the enumerated procedure of Sec. 3):
      energy sum_a theta_a*(k) F_a(k)                            (Sec. 3, steps 3a-3c; eq. enlk)
   5. F_a(r) by inverse FFT                                      (Sec. 3, step 4)
   6. dE/dn, dE/dsigma                                           (Sec. 2, eqs. dedn and dedsigma)
+and, beside the nonlocal path, the semilocal LDA correlation E_c^LDA, v_c^LDA of eq. 1's split
+(PW92, appendix).
 
 Readings where the paper is silent or garbled (each also listed in the design notes):
   * r_s = (3/(4 pi n))^{1/3}, the Wigner-Seitz radius (the appendix prints r_s^3 = 4 pi n/3,
@@ -108,6 +110,25 @@ def pw92_correlation(rs):
     eps = -2.0 * PW92_A * (1.0 + PW92_ALPHA1 * rs) * L
     deps = -2.0 * PW92_A * PW92_ALPHA1 * L + 2.0 * PW92_A * (1.0 + PW92_ALPHA1 * rs) * dQ / (Q * Q + Q)
     return eps, deps
+
+
+def lda_correlation(n, cell):
+    """Semilocal LDA part of the vdW-DF correlation, spin-paired (eq. 1 splits E_c into E_c^LDA +
+    E_c^nl; eps_c is the appendix's PW92 form).
+
+    E_c^LDA = int n eps_c(r_s) dr, as the grid sum (Omega/N) sum_j n_j eps_c(r_s(n_j)) with
+    r_s = (3/(4 pi n))^{1/3};  v_c^LDA = d(n eps_c)/dn = eps_c + n (d eps_c/d r_s)(d r_s/d n)
+    = eps_c - (r_s/3) d eps_c/d r_s.  Vacuum points (n < 1e-30) add nothing and get v = 0.
+    Returns (E, v)."""
+    n = np.asarray(n, dtype=np.float64)
+    cell = np.asarray(cell, dtype=np.float64)
+    dV = float(np.linalg.det(cell)) / n.size
+    live = n >= VACUUM_DENSITY
+    rs = np.where(live, np.cbrt(3.0 / (4.0 * math.pi * np.where(live, n, 1.0))), 1.0)
+    eps, deps = pw92_correlation(rs)
+    v = np.where(live, eps - (rs / 3.0) * deps, 0.0)
+    E = dV * float(np.sum(np.where(live, n * eps, 0.0)))
+    return E, v
 
 
 def saturation(x, a=SATURATION_A):
