@@ -172,6 +172,25 @@ def time_form(f, n, g, steps: int, warmup: int, grid, precision: str, m: int = M
     return ms_per_step, per_stage, roofline, v, float(e.item())
 
 
+def time_lda(f, n, steps: int, npoints: int):
+    """The LDA correlation pass (E_c^LDA, v_c^LDA; FP64 in both precisions) on the same density:
+    per-launch time from the library's HIP events, against its 16 bytes per point."""
+    import torch
+    v = torch.empty_like(n)
+    e = torch.zeros(1, dtype=torch.float64, device=n.device)
+    for _ in range(2):
+        f.lda_async(n, v, e)
+    f.enable_timing(True)
+    for _ in range(steps):
+        f.lda_async(n, v, e)
+    ms, cnt = f.read_timing()["lda"]
+    f.enable_timing(False)
+    avg = ms / cnt
+    gbs = 16.0 * npoints / (avg * 1e-3) / 1e9
+    return {"ms_avg": round(avg, 4), "launches": cnt, "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_per_point": 16, "E_c_lda": float(e.item())}
+
+
 def serving_measurement(kt, count, rate, precision):
     """Poisson stream of `count` energy+potential requests (grids 48..160^3) through the
     continuous-batching server: once with a 64 GB HBM budget, once with the budget capped at 1.25x
@@ -253,10 +272,14 @@ def main() -> int:
 
     forms = [args.precision] + ([] if args.no_second_form else [p for p in ("fp64", "fp32") if p != args.precision])
     results = {}
+    lda = None
     for prec in forms:
         f = vdwxc.Functional(w.grid, w.cell, flavour="DF1", precision=prec, table=kt)
         ms, stages, roof, v, E = time_form(f, n, g, args.steps, args.warmup, w.grid, prec)
         roof["traffic"] = profiled_traffic(args.workload, prec, roof["kernel"])
+        if prec == args.precision:
+            lda = time_lda(f, n, args.steps, w.npoints)
+            say(f"lda correlation: {lda['ms_avg']:.3f} ms, {lda['GBps']:.0f} GB/s")
         f.close()
         results[prec] = dict(ms=ms, stages=stages, roofline=roof, v=v, E=E)
         say(f"{prec}: {ms:.3f} ms/step, {w.npoints / ms * 1e3:.4e} pts/s, E = {E:.12e}, "
@@ -355,6 +378,7 @@ def main() -> int:
         "fp32_mixed" if prec == "fp64" else "fp64": second,
         "serving": serve,
         "q_mesh_10": qmesh,
+        "lda_correlation": lda,
     }
     print(json.dumps(out), flush=True)
     return 0

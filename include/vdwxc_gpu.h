@@ -125,6 +125,18 @@ vdwxc_status vdwxc_calculate_potential_noalloc(vdwxc_handle h, const double* n, 
 vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double* sigma, double* dedn,
                                    double* dedsigma, double* energy_dev);
 
+/* The semilocal LDA part of the vdW-DF correlation (paper eq. 1 splits E_c into E_c^LDA + E_c^nl):
+ * the spin-paired Perdew-Wang (PW92) correlation energy per electron eps_c(r_s) of the paper's
+ * appendix, r_s = (3/(4 pi n))^(1/3).  From the density n (device, [N1][N2][N3]) writes
+ * E_c^LDA = \int n eps_c dr, the grid sum times Omega/N, to the device double energy_dev, and
+ * v_c^LDA = d(n eps_c)/dn = eps_c - (r_s/3) d eps_c/d r_s per point to v (device, [N1][N2][N3];
+ * it must not overlap n, which is rejected with VDWXC_EINVAL when v == n).  Arithmetic is FP64 in
+ * both precisions; one streaming pass (8 bytes read and 8 written per point) and a fixed-order sum,
+ * so equal inputs give equal bits.  Vacuum points (n < 1e-30) give v = 0 and no energy; a NaN in n
+ * gives NaN at that point and in the energy.  Asynchronous on the handle's stream; it uses the
+ * handle's work memory, so it is ordered with the handle's other calls by the stream. */
+vdwxc_status vdwxc_calculate_lda_async(vdwxc_handle h, const double* n, double* v, double* energy_dev);
+
 /* Device memory a handle for this grid allocates for its work buffers (excluding the shared
  * tables), for admission control, with the paper's N_alpha = 20 q-mesh points; 0 if the grid or
  * precision is invalid.  Host-only. */
@@ -162,7 +174,8 @@ typedef enum {
   VDWXC_STAGE_DIV_Z = 8,        /* spectral divergence of 2 dE/dsigma grad n, one axis per pass: */
   VDWXC_STAGE_DIV_Y = 9,        /* z, y, x (the x pass subtracts it from the potential) */
   VDWXC_STAGE_DIV_X = 10,
-  VDWXC_NUM_STAGES = 11
+  VDWXC_STAGE_LDA = 11,         /* LDA correlation pass (vdwxc_calculate_lda_async) */
+  VDWXC_NUM_STAGES = 12
 } vdwxc_stage;
 
 /* Per-stage timing with HIP events recorded on the handle's stream around every kernel launch

@@ -48,6 +48,21 @@ struct alignas(4 * sizeof(T)) Quad {
 
 // ---- q0, saturation and the helper splines (per grid point, FP64) ----------------------------
 
+// PW92 LDA correlation energy per electron eps_c(r_s) of the paper's appendix (spin-paired) and
+// its derivative d eps_c / d r_s
+__device__ __forceinline__ void pw92(double rs, double& eps, double& deps) {
+  const double sq = sqrt(rs);
+  const double Q = 2.0 * kA * (kB1 * sq + kB2 * rs + kB3 * rs * sq + kB4 * rs * rs);
+  const double dQ = 2.0 * kA * (0.5 * kB1 / sq + kB2 + 1.5 * kB3 * sq + 2.0 * kB4 * rs);
+  const double iQ = 1.0 / Q;
+  const double lg = log1p(iQ);
+  eps = -2.0 * kA * (1.0 + kAlpha1 * rs) * lg;
+  deps = -2.0 * kA * kAlpha1 * lg + 2.0 * kA * (1.0 + kAlpha1 * rs) * dQ * iQ / (Q + 1.0);
+}
+
+// r_s = (3 / (4 pi n))^(1/3) through k_F = (3 pi^2 n)^(1/3): k_F r_s = (9 pi / 4)^(1/3)
+constexpr double kRsKf = 1.9191582926775130066248;
+
 // q0 of the appendix with the saturation h_5, clamped below the first mesh point.  Returns the
 // spline interval b (or -1 for a vacuum point), the position t in it, and n*dq0/dn, n*dq0/dsigma.
 __device__ __forceinline__ void q0_state(double n, double sigma, double zab, const double* q, int M,
@@ -61,14 +76,9 @@ __device__ __forceinline__ void q0_state(double n, double sigma, double zab, con
   // k_F r_s = (9 pi / 4)^(1/3), so one cube root and two reciprocals serve all the divisions
   const double kF = cbrt(3.0 * kPi * kPi * n);
   const double inv_n = 1.0 / n, inv_kF = 1.0 / kF;
-  const double rs = 1.9191582926775130066248 * inv_kF;   // (9 pi / 4)^(1/3) / k_F
-  const double sq = sqrt(rs);
-  const double Q = 2.0 * kA * (kB1 * sq + kB2 * rs + kB3 * rs * sq + kB4 * rs * rs);
-  const double dQ = 2.0 * kA * (0.5 * kB1 / sq + kB2 + 1.5 * kB3 * sq + 2.0 * kB4 * rs);
-  const double iQ = 1.0 / Q;
-  const double lg = log1p(iQ);
-  const double eps = -2.0 * kA * (1.0 + kAlpha1 * rs) * lg;
-  const double deps = -2.0 * kA * kAlpha1 * lg + 2.0 * kA * (1.0 + kAlpha1 * rs) * dQ * iQ / (Q + 1.0);
+  const double rs = kRsKf * inv_kF;
+  double eps, deps;
+  pw92(rs, eps, deps);
   const double inv_kn2 = inv_kF * inv_n * inv_n;
   const double x = kF - (4.0 * kPi / 3.0) * eps - (zab / 36.0) * sigma * inv_kn2;
   const double tt = x / kSatA;
@@ -941,6 +951,69 @@ __device__ __forceinline__ void energy_reduce_block(const double* __restrict__ p
     flag[0] = 0;
   }
   __syncthreads();
+}
+
+// ---- semilocal completion: the LDA correlation (appendix, PW92) -----------------------------
+// E_c^LDA = (Omega/N) sum_p n_p eps_c(r_s(n_p)) and v_c^LDA = d(n eps_c)/dn = eps_c - (r_s/3)
+// d eps_c/d r_s per point, in FP64: a streaming pass of 8 bytes read and 8 written per point.
+// Each thread takes kLdaUnroll points a step (their loads issued together), sums n eps_c in a fixed
+// order and the block adds its threads' sums in a fixed tree into partials[block]; k_lda_energy
+// adds the blocks' sums in one block.  Equal inputs give equal bits.  A NaN density yields NaN at
+// its point and in the energy; points below the vacuum threshold give zero.
+constexpr int kLdaThreads = 256, kLdaUnroll = 4, kLdaBlocks = 2048;
+
+__device__ __forceinline__ double block_sum_fixed(double s, double* red, int tid) {
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  double tot = 0.0;
+  if (tid == 0)
+    for (int w = 0; w < kLdaThreads / 64; ++w) tot += red[w];
+  return tot;   // valid in thread 0
+}
+
+__global__ void __launch_bounds__(kLdaThreads) k_lda_pw92(const double* __restrict__ n, double* __restrict__ v,
+                                                         double* __restrict__ partials, long long npts) {
+  __shared__ double red[kLdaThreads / 64];
+  const int tid = threadIdx.x;
+  const long long step = (long long)gridDim.x * kLdaThreads * kLdaUnroll;
+  double acc = 0.0;
+  for (long long p0 = (long long)blockIdx.x * kLdaThreads * kLdaUnroll + tid; p0 < npts; p0 += step) {
+    double x[kLdaUnroll];
+#pragma unroll
+    for (int u = 0; u < kLdaUnroll; ++u) {
+      const long long p = p0 + (long long)u * kLdaThreads;
+      x[u] = p < npts ? n[p] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLdaUnroll; ++u) {
+      const long long p = p0 + (long long)u * kLdaThreads;
+      double vp = 0.0, e = 0.0;
+      if (x[u] >= kVacuum) {
+        const double rs = kRsKf / cbrt(3.0 * kPi * kPi * x[u]);
+        double eps, deps;
+        pw92(rs, eps, deps);
+        vp = eps - (rs / 3.0) * deps;
+        e = x[u] * eps;
+      } else if (x[u] != x[u]) {
+        vp = e = x[u];
+      }
+      if (p < npts) v[p] = vp;
+      acc += e;
+    }
+  }
+  const double tot = block_sum_fixed(acc, red, tid);
+  if (tid == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kLdaThreads) k_lda_energy(const double* __restrict__ partials, int nparts,
+                                                           double scale, double* __restrict__ energy) {
+  __shared__ double red[kLdaThreads / 64];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int i = tid; i < nparts; i += kLdaThreads) acc += partials[i];
+  const double tot = block_sum_fixed(acc, red, tid);
+  if (tid == 0) energy[0] = tot * scale;
 }
 
 // ---- pass 5: inverse z FFT + assembly of dE/dn, dE/dsigma (eqs. dedn, dedsigma) -------------

@@ -139,13 +139,14 @@ struct Work {
   void* state = nullptr;       // per-point spline state Quad<T> [N], theta pass -> assembly
   double* G = nullptr;         // spectral gradient [3][N]
   double* partials = nullptr;  // per-column energy partials [N2 * H3]
+  double* lda = nullptr;       // per-block sums of the LDA correlation pass [kLdaBlocks]
   int* flag = nullptr;         // [0]: NaN seen by the theta pass, [1]: the last evaluation's flag
   bool timed = true;
 };
 
 // byte offsets of the buffers of Work in one block (each 256-byte aligned) and its size
 struct Layout {
-  size_t A, B, S, state, G, partials, flag, total;
+  size_t A, B, S, state, G, partials, lda, flag, total;
 };
 
 // bytes per grid point of the spline state passed from the theta pass to the assembly
@@ -168,6 +169,7 @@ Layout workspace_layout(int n1, int n2, int n3, vdwxc_precision p, int M) {
   L.state = o; o += al(N * state_bytes(p));
   L.G = o; o += al(3 * N * sizeof(double));
   L.partials = o; o += al(size_t(n2) * (n3 / 2 + 1) * sizeof(double));
+  L.lda = o; o += al(kLdaBlocks * sizeof(double));
   L.flag = o; o += al(2 * sizeof(int));
   L.total = o;
   return L;
@@ -182,6 +184,7 @@ Work carve(void* base, const Layout& L) {
   w.state = b + L.state;
   w.G = reinterpret_cast<double*>(b + L.G);
   w.partials = reinterpret_cast<double*>(b + L.partials);
+  w.lda = reinterpret_cast<double*>(b + L.lda);
   w.flag = reinterpret_cast<int*>(b + L.flag);
   return w;
 }
@@ -983,6 +986,19 @@ vdwxc_status run_potential(vdwxc_ctx* h, const Work& w, const double* n, const d
   return finish_launch(h);
 }
 
+vdwxc_status run_lda(vdwxc_ctx* h, const Work& w, const double* n, double* v, double* energy_dev) {
+  HIP_TRY(h, hipSetDevice(h->device));
+  const long long N = (long long)h->n1 * h->n2 * h->n3;
+  const long long per_block = (long long)kLdaThreads * kLdaUnroll;
+  const int blocks = int(std::min<long long>(kLdaBlocks, (N + per_block - 1) / per_block));
+  stage_begin(h, w);
+  hipLaunchKernelGGL(k_lda_pw92, dim3(blocks), dim3(kLdaThreads), 0, h->stream, n, v, w.lda, N);
+  hipLaunchKernelGGL(k_lda_energy, dim3(1), dim3(kLdaThreads), 0, h->stream, w.lda, blocks, h->omega / double(N),
+                     energy_dev);
+  stage_end(h, w, VDWXC_STAGE_LDA);
+  return finish_launch(h);
+}
+
 vdwxc_status read_energy(vdwxc_ctx* h, double* energy_host) {
   HIP_TRY(h, hipMemcpyAsync(h->h_energy, h->d_energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipMemcpyAsync(h->h_flag, h->work.flag + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1371,10 +1387,17 @@ vdwxc_status vdwxc_calculate_potential_noalloc(vdwxc_handle h, const double* n, 
   return run_potential(h, w, n, grad_n, v, energy_dev);
 }
 
+vdwxc_status vdwxc_calculate_lda_async(vdwxc_handle h, const double* n, double* v, double* energy_dev) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (!n || !v || !energy_dev) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  if (n == v) return fail(h, VDWXC_EINVAL, "v must not be the density array");
+  return run_lda(h, h->work, n, v, energy_dev);
+}
+
 const char* vdwxc_stage_name(int stage) {
   static const char* names[VDWXC_NUM_STAGES] = {
       "theta_zfwd", "y_fwd", "x_contract", "y_inv", "z_assemble", "grad_z", "grad_y",
-      "grad_x", "div_z", "div_y", "div_x"};
+      "grad_x", "div_z", "div_y", "div_x", "lda"};
   return (stage >= 0 && stage < VDWXC_NUM_STAGES) ? names[stage] : "?";
 }
 

@@ -38,6 +38,7 @@ SIGNATURES = {
     "vdwxc_calculate_potential": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp]),
     "vdwxc_calculate_potential_async": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                        ctypes.c_void_p]),
+    "vdwxc_calculate_lda_async": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "vdwxc_calculate_potential_noalloc": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                          ctypes.c_void_p]),
     "vdwxc_workspace_bytes": (ctypes.c_size_t, [_ip, ctypes.c_int]),
@@ -52,7 +53,7 @@ SIGNATURES = {
     "vdwxc_read_timing": (ctypes.c_int, [_h, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "vdwxc_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
 }
-NUM_STAGES = 11
+NUM_STAGES = 12
 
 _lib = None
 
@@ -202,6 +203,23 @@ class Functional:
         st = lib().vdwxc_calculate_potential_noalloc(self._h, self._field(n, "n"), gp, self._field(v, "v"),
                                                      ctypes.c_void_p(energy.data_ptr()))
         _check(st, self._h)
+
+    def lda_async(self, n, v, energy):
+        """Enqueue the PW92 LDA correlation: E_c^LDA into the 1-element float64 device tensor
+        `energy`, v_c^LDA into `v`."""
+        self._sync_stream()
+        st = lib().vdwxc_calculate_lda_async(self._h, self._field(n, "n"), self._field(v, "v"),
+                                             ctypes.c_void_p(energy.data_ptr()))
+        _check(st, self._h)
+
+    def lda(self, n, v=None):
+        """(E_c^LDA, v_c^LDA) of the appendix's PW92 correlation; synchronises the stream."""
+        import torch
+        v = torch.empty_like(n) if v is None else v
+        e = torch.empty(1, dtype=torch.float64, device=n.device)
+        self.lda_async(n, v, e)
+        torch.cuda.synchronize(n.device)
+        return float(e.item()), v
 
     def enable_timing(self, enable: bool = True):
         """Record HIP events around every kernel launch of this handle (see read_timing)."""
