@@ -37,6 +37,7 @@ struct Geometry {
   double kmax, inv_dk;     // kernel table range and inverse node spacing
   int nk;                  // kernel table nodes
   double bn2[3];           // |b_i|^2 (used when the cell is orthogonal)
+  int xpair;               // |G| even in kx, bitwise, with N1 even: paired table reads (contraction)
 };
 
 // four values of the path's precision in one aligned load: a kernel-table entry, or the spline
@@ -633,34 +634,67 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 // per two pairs and one FMA per interpolation.  Every lane reads its own nodes; kx and -kx, which
 // have the same |G| in orthogonal cells, sit in adjacent lanes and share them.
 
-// Index of the unordered pair (a <= b), ordered by the larger index b: (0,0), (0,1), (1,1), (0,2),
-// ...  The pairs of a q-mesh of M points are then exactly the first M(M+1)/2, so a shorter mesh
-// reads and contracts only those.  kPairs lists (row a, col b) in this order.
-__host__ __device__ constexpr int pair_index(int a, int b) { return b * (b + 1) / 2 + a; }
+// q-mesh buckets of the contraction kernel (its MB parameter): the smallest of 8, 10, 12, 16, 20
+// that holds M
+__host__ __device__ constexpr int q_bucket(int M) { return M <= 8 ? 8 : M <= 10 ? 10 : M <= 12 ? 12 : M <= 16 ? 16 : 20; }
+
+// Order of the unordered pairs (a <= b) in the table and the contraction.  The pairs of a bucket
+// MB come first: segment s holds the pairs whose larger index lies in [bucket s-1, bucket s), so
+// a mesh of M <= MB points reads and contracts only the first MB(MB+1)/2.  Within a segment the
+// pairs are scheduled greedily so that each one updates the accumulators F_a, F_b that have
+// waited longest since their last update: consecutive FMAs into one accumulator would form a
+// dependency chain (in plain row order every pair of a column updates F_b).
 constexpr int kNumPairs = kMaxQ * (kMaxQ + 1) / 2;
 static_assert(kNumPairs % 2 == 0, "pairs are stored two per table entry");
 struct PairList {
   int row[kNumPairs], col[kNumPairs];
-  constexpr PairList() : row(), col() {
-    int p = 0;
-    for (int b = 0; b < kMaxQ; ++b)
-      for (int a = 0; a <= b; ++a) {
-        row[p] = a;
-        col[p] = b;
+  int pos[kMaxQ][kMaxQ];   // place of pair (a, b), either order
+  constexpr PairList() : row(), col(), pos() {
+    bool used[kMaxQ][kMaxQ] = {};
+    int last[kMaxQ] = {};
+    for (int a = 0; a < kMaxQ; ++a) last[a] = -kNumPairs;
+    const int ends[5] = {8, 10, 12, 16, 20};
+    int p = 0, lo = 0;
+    for (int s = 0; s < 5; ++s) {
+      const int hi = ends[s];
+      const int count = hi * (hi + 1) / 2 - lo * (lo + 1) / 2;
+      for (int k = 0; k < count; ++k) {
+        int ba = -1, bb = -1, best = -1;
+        for (int b = lo; b < hi; ++b)
+          for (int a = 0; a <= b; ++a) {
+            if (used[a][b]) continue;
+            const int da = p - last[a], db = p - last[b];
+            const int score = da < db ? da : db;
+            if (score > best) {
+              best = score;
+              ba = a;
+              bb = b;
+            }
+          }
+        used[ba][bb] = true;
+        row[p] = ba;
+        col[p] = bb;
+        pos[ba][bb] = pos[bb][ba] = p;
+        last[ba] = last[bb] = p;
         ++p;
       }
+      lo = hi;
+    }
   }
 };
 constexpr PairList kPairs{};
-
-// q-mesh buckets of the contraction kernel (its MB parameter): the smallest of 8, 10, 12, 16, 20
-// that holds M
-__host__ __device__ constexpr int q_bucket(int M) { return M <= 8 ? 8 : M <= 10 ? 10 : M <= 12 ? 12 : M <= 16 ? 16 : 20; }
+static_assert(kPairs.pos[0][0] < 36 && kPairs.pos[7][7] < 36 && kPairs.pos[0][8] >= 36, "bucket prefix order");
 
 #ifndef VDWXC_XCHUNK
 #define VDWXC_XCHUNK 3
 #endif
 constexpr int kXChunk = VDWXC_XCHUNK;   // table entries per load chunk of the contraction
+#ifndef VDWXC_XEDGE
+#define VDWXC_XEDGE 0        // paired reads in the wave of kx = 0 and N1/2 as well
+#endif
+#ifndef VDWXC_XRING_HALF
+#define VDWXC_XRING_HALF 3   // chunks of the paired contraction's load ring
+#endif
 
 
 // raw buffer resource, dword 3 on gfx9: no format conversion, plain byte addressing
@@ -676,6 +710,31 @@ __device__ __forceinline__ void buffer_load_quad(__amdgpu_buffer_rsrc_t r, int v
   __builtin_memcpy(&q.x, &lo, 16);
   __builtin_memcpy(&q.z, &hi, 16);
 }
+
+// one half (T_j, D_j of one pair) of a table entry
+__device__ __forceinline__ void buffer_load_half(__amdgpu_buffer_rsrc_t r, int voff, int soff, float2& h) {
+  const auto raw = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  __builtin_memcpy(&h, &raw, sizeof(h));
+}
+__device__ __forceinline__ void buffer_load_half(__amdgpu_buffer_rsrc_t r, int voff, int soff, double2& h) {
+  const auto raw = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  __builtin_memcpy(&h, &raw, sizeof(h));
+}
+
+// x of lane (lane & ~3) + P[lane & 3] (DPP quad permutation CTRL), all four lanes active
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp(int(b), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+constexpr int kDppEvenOfPair = 0xA0;   // quad_perm [0, 0, 2, 2]
+constexpr int kDppOddOfPair = 0xF5;    // quad_perm [1, 1, 3, 3]
 
 // body(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time
 template <int N, typename Body>
@@ -765,8 +824,8 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     int j = inside ? int(floor(sc)) : 0;
     if (j > g.nk - 2) j = g.nk - 2;
     const T w = T(inside ? sc - j : 0.0);
-    // Table entry (group g, node j) = T_j of pairs 2g and 2g+1, then their differences
-    // T_j+1 - T_j, so phi = T_j + w (T_j+1 - T_j) is one FMA.  The entries are stored chunk-major,
+    // Table entry (group g, node j) = T_j and T_j+1 - T_j of pair 2g, then of pair 2g+1, so
+    // phi = T_j + w (T_j+1 - T_j) is one FMA.  The entries are stored chunk-major,
     // [g / kXChunk][j][g % kXChunk]: the kXChunk entries a lane reads for one chunk are adjacent,
     // so a chunk's loads share cache lines.  Buffer loads: the lane's node offset in one VGPR
     // (plus the entry's place in the chunk as an immediate), the chunk's offset in an SGPR,
@@ -774,6 +833,12 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     // chunk offsets are formed up front and stay live).  Each pair is read and interpolated once
     // (phi is symmetric) and feeds F_a += phi theta_b and F_b += phi theta_a.  The next chunk's
     // loads are issued before the current chunk's arithmetic.
+    // Paired reads (FP64 with g.xpair): the lanes of a kx, -kx pair have the same node j and
+    // weight w, so the even lane reads and interpolates pair 2g, the odd lane pair 2g+1, and the
+    // two phis are swapped between them by DPP: half the table bytes per k-point (the
+    // contraction's loads are bound by the vector memory pipeline).  The wave holding kx = 0 and
+    // N1/2 (slots 0 and 1, whose |G| differ) reads whole entries.  (FP32 keeps whole-entry reads:
+    // its register-capped kernel spills with the paired path.)
     constexpr int kPairsMB = MB * (MB + 1) / 2;
     constexpr int kGroups = (kPairsMB + 1) / 2;
     constexpr int kChunks = (kGroups + kXChunk - 1) / kXChunk;
@@ -782,55 +847,102 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     const int cstride = g.nk * (kXChunk * kQ);
     const __amdgpu_buffer_rsrc_t trs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<Quad<T>*>(table4), short(0), cstride * kChunks, kBufferWord3);
-    int tcur = 0;
-#define VDWXC_TLOAD_CHUNK(dst, cc)                                                                \
-  do {                                                                                            \
-    asm volatile("" : "+s"(tcur));                                                                \
-    _Pragma("unroll") for (int i = 0; i < kXChunk; ++i)                                           \
-      if ((cc) * kXChunk + i < kGroups) buffer_load_quad(trs, joff + i * kQ, tcur, (dst)[i]);     \
-    tcur += cstride;                                                                              \
-  } while (0)
-    Quad<T> buf[2][kXChunk];
-    VDWXC_TLOAD_CHUNK(buf[0], 0);
+    constexpr bool kPairable = sizeof(T) == 8;
+    auto contract = [&](auto half_tag, auto edge_tag) {
+      constexpr bool HALF = decltype(half_tag)::value, EDGE = decltype(edge_tag)::value;
+      using Buf = std::conditional_t<HALF, T2, Quad<T>>;
+      const int odd = tid & 1;
+      const int voff = HALF ? joff + odd * (kQ / 2) : joff;
+      // EDGE: the wave of kx = 0 and N1/2 (lanes 0 and 1), which also read the other half of
+      // each entry; the other lanes' second reads repeat their first (no lane branches)
+      const bool edge_lane = EDGE && (tid & 63) < 2;
+      const int voff2 = edge_lane ? joff + (odd ^ 1) * (kQ / 2) : voff;
+      int tcur = 0;
+      auto load_chunk = [&](Buf* dst, T2* dst2, int cc) {
+        asm volatile("" : "+s"(tcur));
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
-      if (c + 1 < kChunks) VDWXC_TLOAD_CHUNK(buf[(c + 1) & 1], c + 1);
-#pragma unroll
-      for (int i = 0; i < kXChunk; ++i) {
-        const int grp = c * kXChunk + i;
-        if (grp < kGroups) {
-          const Quad<T>& v = buf[c & 1][i];
-          const int a0 = kPairs.row[2 * grp], b0 = kPairs.col[2 * grp];
-          const int a1 = kPairs.row[2 * grp + 1], b1 = kPairs.col[2 * grp + 1];
-          const T phi0 = v.x + w * v.z;
-          const T phi1 = v.y + w * v.w;
-#pragma unroll
-          for (int q = 0; q < NPT; ++q) {
-            F[q][a0].x += phi0 * th[q][b0].x;
-            F[q][a0].y += phi0 * th[q][b0].y;
-            if (a0 != b0) {
-              F[q][b0].x += phi0 * th[q][a0].x;
-              F[q][b0].y += phi0 * th[q][a0].y;
+        for (int i = 0; i < kXChunk; ++i)
+          if (cc * kXChunk + i < kGroups) {
+            if constexpr (HALF) {
+              buffer_load_half(trs, voff + i * kQ, tcur, dst[i]);
+              if constexpr (EDGE) buffer_load_half(trs, voff2 + i * kQ, tcur, dst2[i]);
+            } else {
+              buffer_load_quad(trs, voff + i * kQ, tcur, dst[i]);
             }
-            if (2 * grp + 1 < kPairsMB) {   // an odd pair count leaves the last entry half used
-              F[q][a1].x += phi1 * th[q][b1].x;
-              F[q][a1].y += phi1 * th[q][b1].y;
-              if (a1 != b1) {
-                F[q][b1].x += phi1 * th[q][a1].x;
-                F[q][b1].y += phi1 * th[q][a1].y;
+          }
+        tcur += cstride;
+      };
+      // a ring of R chunks: chunk c + R - 1 is loaded while chunk c is contracted (the paired
+      // path's entries are half as large, so it keeps twice the loads in flight in the same
+      // registers)
+      constexpr int R = HALF ? (EDGE ? 2 : VDWXC_XRING_HALF) : 2;
+      Buf buf[R][kXChunk];
+      T2 buf2[R][EDGE ? kXChunk : 1];
+#pragma unroll
+      for (int c = 0; c < R - 1; ++c)
+        if (c < kChunks) load_chunk(buf[c], buf2[c], c);
+#pragma unroll
+      for (int c = 0; c < kChunks; ++c) {
+        if (c + R - 1 < kChunks) load_chunk(buf[(c + R - 1) % R], buf2[(c + R - 1) % R], c + R - 1);
+#pragma unroll
+        for (int i = 0; i < kXChunk; ++i) {
+          const int grp = c * kXChunk + i;
+          if (grp < kGroups) {
+            const int a0 = kPairs.row[2 * grp], b0 = kPairs.col[2 * grp];
+            const int a1 = kPairs.row[2 * grp + 1], b1 = kPairs.col[2 * grp + 1];
+            T phi0, phi1;
+            if constexpr (HALF) {
+              const T2& hv = buf[c % R][i];
+              const T own = hv.x + w * hv.y;
+              phi0 = quad_perm<kDppEvenOfPair>(own);
+              phi1 = quad_perm<kDppOddOfPair>(own);
+              if constexpr (EDGE) {
+                const T2& ov = buf2[c % R][i];
+                const T oth = ov.x + w * ov.y;
+                if (edge_lane) {
+                  phi0 = odd ? oth : own;
+                  phi1 = odd ? own : oth;
+                }
+              }
+            } else {
+              const Quad<T>& v = buf[c % R][i];
+              phi0 = v.x + w * v.y;
+              phi1 = v.z + w * v.w;
+            }
+#pragma unroll
+            for (int q = 0; q < NPT; ++q) {
+              F[q][a0].x += phi0 * th[q][b0].x;
+              F[q][a0].y += phi0 * th[q][b0].y;
+              if (a0 != b0) {
+                F[q][b0].x += phi0 * th[q][a0].x;
+                F[q][b0].y += phi0 * th[q][a0].y;
+              }
+              if (2 * grp + 1 < kPairsMB) {   // an odd pair count leaves the last entry half used
+                F[q][a1].x += phi1 * th[q][b1].x;
+                F[q][a1].y += phi1 * th[q][b1].y;
+                if (a1 != b1) {
+                  F[q][b1].x += phi1 * th[q][a1].x;
+                  F[q][b1].y += phi1 * th[q][a1].y;
+                }
               }
             }
           }
         }
+        // pin the accumulators here, so this chunk's arithmetic is not moved below the next
+        // chunk's loads (which would keep every loaded entry live at once)
+#pragma unroll
+        for (int q = 0; q < NPT; ++q)
+#pragma unroll
+          for (int a = 0; a < MB; ++a) asm volatile("" : "+v"(F[q][a].x), "+v"(F[q][a].y));
       }
-      // pin the accumulators here, so this chunk's arithmetic is not moved below the next
-      // chunk's loads (which would keep every loaded entry live at once)
-#pragma unroll
-      for (int q = 0; q < NPT; ++q)
-#pragma unroll
-        for (int a = 0; a < MB; ++a) asm volatile("" : "+v"(F[q][a].x), "+v"(F[q][a].y));
+    };
+    if (kPairable && g.xpair != 0) {
+      if (__builtin_amdgcn_readfirstlane(slot) != 0) contract(std::true_type{}, std::false_type{});
+      else if (VDWXC_XEDGE) contract(std::true_type{}, std::true_type{});
+      else contract(std::false_type{}, std::false_type{});
+    } else {
+      contract(std::false_type{}, std::false_type{});
     }
-#undef VDWXC_TLOAD_CHUNK
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
       if (valid[q]) {

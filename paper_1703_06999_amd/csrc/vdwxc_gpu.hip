@@ -623,16 +623,17 @@ size_t pair_table_bytes(vdwxc_precision p, int nk) {
 
 // The kernel table reordered for the contraction: per unordered pair p = (a <= b) (pair_index
 // order, so the pairs of a q-mesh of M points are the first M(M+1)/2) and node j, T_j and
-// T_j+1 - T_j (0 at the last node).  Pairs 2g and 2g+1 share entry (g, j) = (T_j(2g), T_j(2g+1),
-// D_j(2g), D_j(2g+1)), stored chunk-major at [g / kXChunk][j][g % kXChunk] (the contraction reads
-// a chunk's entries of one node together).  Pairs with a or b >= nq stay zero.
+// T_j+1 - T_j (0 at the last node).  Pairs 2g and 2g+1 share entry (g, j) = (T_j(2g), D_j(2g),
+// T_j(2g+1), D_j(2g+1)), stored chunk-major at [g / kXChunk][j][g % kXChunk] (the contraction reads
+// a chunk's entries of one node together; the two lanes of a kx, -kx pair read one half each).
+// Pairs with a or b >= nq stay zero.
 std::vector<Quad<double>> build_pair_table(int nq, int nk, const double* table) {
   constexpr int kGroups = kNumPairs / 2, kChunks = (kGroups + kXChunk - 1) / kXChunk;
   const size_t tn = size_t(kChunks) * kXChunk * nk;
   std::vector<Quad<double>> t64(tn, Quad<double>{0.0, 0.0, 0.0, 0.0});
   for (int a = 0; a < nq; ++a)
     for (int b = a; b < nq; ++b) {
-      const int pr = pair_index(a, b);
+      const int pr = kPairs.pos[a][b];
       for (int j = 0; j < nk; ++j) {
         const double tj = table[(size_t(j) * nq + a) * nq + b];
         const double dj = j + 1 < nk ? table[(size_t(j + 1) * nq + a) * nq + b] - tj : 0.0;
@@ -640,9 +641,9 @@ std::vector<Quad<double>> build_pair_table(int nq, int nk, const double* table) 
         Quad<double>& q = t64[(size_t(grp / kXChunk) * nk + j) * kXChunk + grp % kXChunk];
         if (pr % 2 == 0) {
           q.x = tj;
-          q.z = dj;
+          q.y = dj;
         } else {
-          q.y = tj;
+          q.z = tj;
           q.w = dj;
         }
       }
@@ -1118,6 +1119,9 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
       }
     h->ortho = ortho;
   }
+  // |G| is even in kx exactly (bitwise, as the kernels compute it) when b1 has no y, z and b2, b3
+  // no x component: then the kx and -kx lanes of the contraction share one table read
+  g.xpair = (h->n1 % 2 == 0) && g.bvec[1] == 0.0 && g.bvec[2] == 0.0 && g.bvec[3] == 0.0 && g.bvec[6] == 0.0;
   if (!(max_gnorm2(n, g.bvec) < kmax * kmax)) {
     release(h);
     return fail(nullptr, VDWXC_EINVAL, "grid reaches |G| >= kmax of the kernel table (grid too fine)");
@@ -1452,7 +1456,8 @@ vdwxc_status vdwxc_print(vdwxc_handle h) {
               h->flavour == VDWXC_DF1 ? "vdW-DF1" : "vdW-DF2", h->geo.zab,
               h->precision == VDWXC_FP64 ? "FP64" : "FP32_MIXED", h->M, h->qmesh.front(), h->qmesh.back(), h->nk,
               h->M, h->M, h->kmax);
-  std::printf("  work buffers 2 x %.3f MB, device %d\n", h->buf_bytes / 1e6, h->device);
+  std::printf("  work buffers 2 x %.3f MB, work memory %.3f MB at %p, device %d\n", h->buf_bytes / 1e6,
+              h->ws_bytes / 1e6, h->d_ws, h->device);
   std::fflush(stdout);
   return VDWXC_OK;
 }

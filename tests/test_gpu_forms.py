@@ -117,7 +117,7 @@ def test_autograd_backward_matches_oracle_potential_192(dev, c3):
         E = vdwxc_energy(x, f)
         E.backward()
         g = x.grad.cpu().numpy() / dV
-        e_err = abs(float(E) - E_ref) / abs(E_ref)
+        e_err = abs(float(E.detach()) - E_ref) / abs(E_ref)
         v_err = np.max(np.abs(g - v_ref)) / np.max(np.abs(v_ref))
         say(f"    {prec}: E rel {e_err:.2e}, v max-norm rel {v_err:.2e}")
         assert e_err <= tol_e and v_err <= tol_v
