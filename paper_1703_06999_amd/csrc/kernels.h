@@ -689,9 +689,6 @@ static_assert(kPairs.pos[0][0] < 36 && kPairs.pos[7][7] < 36 && kPairs.pos[0][8]
 #define VDWXC_XCHUNK 3
 #endif
 constexpr int kXChunk = VDWXC_XCHUNK;   // table entries per load chunk of the contraction
-#ifndef VDWXC_XEDGE
-#define VDWXC_XEDGE 0        // paired reads in the wave of kx = 0 and N1/2 as well
-#endif
 #ifndef VDWXC_XRING_HALF
 #define VDWXC_XRING_HALF 3   // chunks of the paired contraction's load ring
 #endif
@@ -848,42 +845,32 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     const __amdgpu_buffer_rsrc_t trs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<Quad<T>*>(table4), short(0), cstride * kChunks, kBufferWord3);
     constexpr bool kPairable = sizeof(T) == 8;
-    auto contract = [&](auto half_tag, auto edge_tag) {
-      constexpr bool HALF = decltype(half_tag)::value, EDGE = decltype(edge_tag)::value;
+    auto contract = [&](auto half_tag) {
+      constexpr bool HALF = decltype(half_tag)::value;
       using Buf = std::conditional_t<HALF, T2, Quad<T>>;
-      const int odd = tid & 1;
-      const int voff = HALF ? joff + odd * (kQ / 2) : joff;
-      // EDGE: the wave of kx = 0 and N1/2 (lanes 0 and 1), which also read the other half of
-      // each entry; the other lanes' second reads repeat their first (no lane branches)
-      const bool edge_lane = EDGE && (tid & 63) < 2;
-      const int voff2 = edge_lane ? joff + (odd ^ 1) * (kQ / 2) : voff;
+      const int voff = HALF ? joff + (tid & 1) * (kQ / 2) : joff;
       int tcur = 0;
-      auto load_chunk = [&](Buf* dst, T2* dst2, int cc) {
+      auto load_chunk = [&](Buf* dst, int cc) {
         asm volatile("" : "+s"(tcur));
 #pragma unroll
         for (int i = 0; i < kXChunk; ++i)
           if (cc * kXChunk + i < kGroups) {
-            if constexpr (HALF) {
-              buffer_load_half(trs, voff + i * kQ, tcur, dst[i]);
-              if constexpr (EDGE) buffer_load_half(trs, voff2 + i * kQ, tcur, dst2[i]);
-            } else {
-              buffer_load_quad(trs, voff + i * kQ, tcur, dst[i]);
-            }
+            if constexpr (HALF) buffer_load_half(trs, voff + i * kQ, tcur, dst[i]);
+            else buffer_load_quad(trs, voff + i * kQ, tcur, dst[i]);
           }
         tcur += cstride;
       };
       // a ring of R chunks: chunk c + R - 1 is loaded while chunk c is contracted (the paired
       // path's entries are half as large, so it keeps twice the loads in flight in the same
       // registers)
-      constexpr int R = HALF ? (EDGE ? 2 : VDWXC_XRING_HALF) : 2;
+      constexpr int R = HALF ? VDWXC_XRING_HALF : 2;
       Buf buf[R][kXChunk];
-      T2 buf2[R][EDGE ? kXChunk : 1];
 #pragma unroll
       for (int c = 0; c < R - 1; ++c)
-        if (c < kChunks) load_chunk(buf[c], buf2[c], c);
+        if (c < kChunks) load_chunk(buf[c], c);
 #pragma unroll
       for (int c = 0; c < kChunks; ++c) {
-        if (c + R - 1 < kChunks) load_chunk(buf[(c + R - 1) % R], buf2[(c + R - 1) % R], c + R - 1);
+        if (c + R - 1 < kChunks) load_chunk(buf[(c + R - 1) % R], c + R - 1);
 #pragma unroll
         for (int i = 0; i < kXChunk; ++i) {
           const int grp = c * kXChunk + i;
@@ -896,14 +883,6 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
               const T own = hv.x + w * hv.y;
               phi0 = quad_perm<kDppEvenOfPair>(own);
               phi1 = quad_perm<kDppOddOfPair>(own);
-              if constexpr (EDGE) {
-                const T2& ov = buf2[c % R][i];
-                const T oth = ov.x + w * ov.y;
-                if (edge_lane) {
-                  phi0 = odd ? oth : own;
-                  phi1 = odd ? own : oth;
-                }
-              }
             } else {
               const Quad<T>& v = buf[c % R][i];
               phi0 = v.x + w * v.y;
@@ -936,13 +915,8 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
           for (int a = 0; a < MB; ++a) asm volatile("" : "+v"(F[q][a].x), "+v"(F[q][a].y));
       }
     };
-    if (kPairable && g.xpair != 0) {
-      if (__builtin_amdgcn_readfirstlane(slot) != 0) contract(std::true_type{}, std::false_type{});
-      else if (VDWXC_XEDGE) contract(std::true_type{}, std::true_type{});
-      else contract(std::false_type{}, std::false_type{});
-    } else {
-      contract(std::false_type{}, std::false_type{});
-    }
+    if (kPairable && g.xpair != 0 && __builtin_amdgcn_readfirstlane(slot) != 0) contract(std::true_type{});
+    else contract(std::false_type{});
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
       if (valid[q]) {
