@@ -685,10 +685,16 @@ struct PairList {
 constexpr PairList kPairs{};
 static_assert(kPairs.pos[0][0] < 36 && kPairs.pos[7][7] < 36 && kPairs.pos[0][8] >= 36, "bucket prefix order");
 
-#ifndef VDWXC_XCHUNK
-#define VDWXC_XCHUNK 3
+// table entries per load chunk of the contraction: FP64 3 (96 bytes of one node), FP32 2 (the
+// register-capped FP32 kernel spills less with the smaller double buffer)
+#ifndef VDWXC_XCHUNK64
+#define VDWXC_XCHUNK64 3
 #endif
-constexpr int kXChunk = VDWXC_XCHUNK;   // table entries per load chunk of the contraction
+#ifndef VDWXC_XCHUNK32
+#define VDWXC_XCHUNK32 2
+#endif
+template <typename T>
+__host__ __device__ constexpr int x_chunk() { return sizeof(T) == 8 ? VDWXC_XCHUNK64 : VDWXC_XCHUNK32; }
 #ifndef VDWXC_XRING_HALF
 #define VDWXC_XRING_HALF 3   // chunks of the paired contraction's load ring
 #endif
@@ -836,6 +842,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     // contraction's loads are bound by the vector memory pipeline).  The wave holding kx = 0 and
     // N1/2 (slots 0 and 1, whose |G| differ) reads whole entries.  (FP32 keeps whole-entry reads:
     // its register-capped kernel spills with the paired path.)
+    constexpr int kXChunk = x_chunk<T>();
     constexpr int kPairsMB = MB * (MB + 1) / 2;
     constexpr int kGroups = (kPairsMB + 1) / 2;
     constexpr int kChunks = (kGroups + kXChunk - 1) / kXChunk;

@@ -614,22 +614,25 @@ void release(vdwxc_ctx* h) {
   delete h;
 }
 
+// load chunk (groups of two pairs) of the contraction kernel in precision p
+int table_chunk(vdwxc_precision p) { return p == VDWXC_FP64 ? x_chunk<double>() : x_chunk<float>(); }
+
 // Device bytes of the contraction's pair table: per group of two unordered pairs and node j one
-// Quad (T_j of both pairs, then T_j+1 - T_j of both), padded to whole chunks of kXChunk groups.
+// Quad (T_j and T_j+1 - T_j of each pair), padded to whole chunks of the precision's chunk.
 size_t pair_table_bytes(vdwxc_precision p, int nk) {
-  constexpr int kGroups = kNumPairs / 2, kChunks = (kGroups + kXChunk - 1) / kXChunk;
-  return size_t(kChunks) * kXChunk * size_t(nk) * (p == VDWXC_FP64 ? sizeof(Quad<double>) : sizeof(Quad<float>));
+  const int ch = table_chunk(p), chunks = (kNumPairs / 2 + ch - 1) / ch;
+  return size_t(chunks) * ch * size_t(nk) * (p == VDWXC_FP64 ? sizeof(Quad<double>) : sizeof(Quad<float>));
 }
 
 // The kernel table reordered for the contraction: per unordered pair p = (a <= b) (pair_index
 // order, so the pairs of a q-mesh of M points are the first M(M+1)/2) and node j, T_j and
 // T_j+1 - T_j (0 at the last node).  Pairs 2g and 2g+1 share entry (g, j) = (T_j(2g), D_j(2g),
-// T_j(2g+1), D_j(2g+1)), stored chunk-major at [g / kXChunk][j][g % kXChunk] (the contraction reads
+// T_j(2g+1), D_j(2g+1)), stored chunk-major at [g / ch][j][g % ch] (the contraction reads
 // a chunk's entries of one node together; the two lanes of a kx, -kx pair read one half each).
 // Pairs with a or b >= nq stay zero.
-std::vector<Quad<double>> build_pair_table(int nq, int nk, const double* table) {
-  constexpr int kGroups = kNumPairs / 2, kChunks = (kGroups + kXChunk - 1) / kXChunk;
-  const size_t tn = size_t(kChunks) * kXChunk * nk;
+std::vector<Quad<double>> build_pair_table(int nq, int nk, const double* table, int ch) {
+  const int chunks = (kNumPairs / 2 + ch - 1) / ch;
+  const size_t tn = size_t(chunks) * ch * nk;
   std::vector<Quad<double>> t64(tn, Quad<double>{0.0, 0.0, 0.0, 0.0});
   for (int a = 0; a < nq; ++a)
     for (int b = a; b < nq; ++b) {
@@ -638,7 +641,7 @@ std::vector<Quad<double>> build_pair_table(int nq, int nk, const double* table) 
         const double tj = table[(size_t(j) * nq + a) * nq + b];
         const double dj = j + 1 < nk ? table[(size_t(j + 1) * nq + a) * nq + b] - tj : 0.0;
         const int grp = pr / 2;
-        Quad<double>& q = t64[(size_t(grp / kXChunk) * nk + j) * kXChunk + grp % kXChunk];
+        Quad<double>& q = t64[(size_t(grp / ch) * nk + j) * ch + grp % ch];
         if (pr % 2 == 0) {
           q.x = tj;
           q.y = dj;
@@ -680,7 +683,7 @@ hipError_t acquire_table(int device, vdwxc_precision precision, int nq, const do
   hipError_t e = upload(&t->d_q, qmesh, nq);
   if (e == hipSuccess) e = upload(&t->d_mm, mm.data(), mm.size());
   if (e == hipSuccess) {
-    const std::vector<Quad<double>> t64 = build_pair_table(nq, nk, table);
+    const std::vector<Quad<double>> t64 = build_pair_table(nq, nk, table, table_chunk(precision));
     if (precision == VDWXC_FP64) {
       e = upload(&t->d_table64, t64.data(), t64.size());
     } else {
