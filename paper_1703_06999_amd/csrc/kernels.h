@@ -1292,17 +1292,15 @@ k_zinv_assemble512(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __
   const int yl = __builtin_amdgcn_readfirstlane(tid >> 6), i = tid & 63, y = y0 + yl;
   const bool live = y < g.n2;
   const size_t pbase = (size_t(x) * g.n2 + y) * n3 + i;
-  // the spline state of the thread's points, as the forward theta pass left it
+  // the spline interval of the thread's points, as the forward theta pass left it (the rest of
+  // the state, t, n dq0/dn and n dq0/dsigma, is read again after the transforms, which keeps it
+  // out of the registers the transforms need)
   int pb[8];
-  T pt[8], pan[8], pas[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     Quad<T> q{T(0), T(0), T(0), T(255)};
     if (live) q = state[pbase + 64 * r];
     pb[r] = int(q.w);
-    pt[r] = q.x;
-    pan[r] = q.y;
-    pas[r] = q.z;
   }
   // Per point, with F_a the inverse transforms and m_c,a = p_a''(q_c):
   //   sum_a F_a p_a  = u F_b + t F_b+1 + c6 [(u^3-u) X0 + (t^3-t) X1]
@@ -1360,12 +1358,15 @@ k_zinv_assemble512(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __
   }
   if (live) {
     const double invN = 1.0 / double(N);
+    Quad<T> st[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) st[r] = state[pbase + 64 * r];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       double vn = 0.0, vs = 0.0;
       const int b = pb[r];
       if (b != 255) {
-        const double t = pt[r], an = pan[r], as = pas[r];
+        const double t = st[r].x, an = st[r].y, as = st[r].z;
         const double hh = S.h[b], c6 = S.c6[b], u = 1.0 - t;
         const double fb0 = Fb[r], fb1 = Fb1[r];
         const double P = u * fb0 + t * fb1 + c6 * ((u * u * u - u) * X0[r] + (t * t * t - t) * X1[r]);

@@ -76,7 +76,7 @@ constexpr bool a512_used() { return sizeof(T) == 8 ? true : VDWXC_A512_FP32; }
 template <typename T>
 constexpr int a512_wpe() { return sizeof(T) == 8 ? VDWXC_A512_WPE64 : VDWXC_A512_WPE32; }
 #ifndef VDWXC_A512_PF64
-#define VDWXC_A512_PF64 0
+#define VDWXC_A512_PF64 1
 #endif
 #ifndef VDWXC_A512_PF32
 #define VDWXC_A512_PF32 0
