@@ -83,6 +83,29 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
                               vdwxc_precision precision, int nq, const double* qmesh, int nk, double kmax,
                               const double* table, void* hip_stream);
 
+/* Flags of vdwxc_init_table_ex. */
+#define VDWXC_INIT_NO_WORKSPACE 1u /* the handle allocates no work memory: attach some with vdwxc_set_workspace */
+
+/* As vdwxc_init_table, with flags (0 or VDWXC_INIT_NO_WORKSPACE; other bits give VDWXC_EINVAL).  With
+ * VDWXC_INIT_NO_WORKSPACE the handle holds its plans and the shared tables but no work memory, so
+ * it is cheap to keep many resident (e.g. one per grid shape and stream of a server); its calculate
+ * calls return VDWXC_ESTATE until work memory is attached with vdwxc_set_workspace.  Nothing is
+ * synchronised in that case. */
+vdwxc_status vdwxc_init_table_ex(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
+                                 vdwxc_precision precision, int nq, const double* qmesh, int nk, double kmax,
+                                 const double* table, void* hip_stream, unsigned flags);
+
+/* Run the handle's later calculate calls (all but vdwxc_calculate_potential_noalloc) in caller-owned
+ * device memory: workspace, 256-byte aligned, of bytes >= vdwxc_workspace_bytes_m(grid, precision,
+ * N_alpha) (else VDWXC_EINVAL and nothing changes).  The caller keeps ownership, must keep the memory
+ * alive until the stream has passed the work enqueued with it, and must not let two handles use it
+ * at the same time (their streams would race).  workspace NULL returns the handle to its own work
+ * memory (none for a VDWXC_INIT_NO_WORKSPACE handle).  The handle's own memory is kept, not freed, so
+ * the call never synchronises: it only enqueues a small kernel on the handle's stream that clears the
+ * NaN flags held in the work memory.  For pools of work buffers shared between handles, so that
+ * switching a request to another buffer allocates and frees nothing. */
+vdwxc_status vdwxc_set_workspace(vdwxc_handle h, void* workspace, size_t bytes);
+
 /* The paper's evaluation (Sec. 3 steps 1-5, Sec. 6 step 4): from the density n and
  * sigma = |grad n|^2 (device, [N1][N2][N3]) compute the energy E_c^nl (written to *energy_host,
  * a host pointer) and the partial derivatives dedn = dE/dn|_sigma, dedsigma = dE/dsigma|_n per

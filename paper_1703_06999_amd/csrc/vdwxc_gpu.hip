@@ -955,6 +955,13 @@ vdwxc_status check_handle(vdwxc_ctx* h) {
   return VDWXC_OK;
 }
 
+// the handle and work memory for a call that runs in the handle's own (or attached) work memory
+vdwxc_status check_work(vdwxc_ctx* h) {
+  if (!h) return VDWXC_ESTATE;
+  if (!h->work.A) return fail(h, VDWXC_ESTATE, "handle has no work memory (created without it; see vdwxc_set_workspace)");
+  return VDWXC_OK;
+}
+
 vdwxc_status finish_launch(vdwxc_ctx* h) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(h, VDWXC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -1048,7 +1055,14 @@ size_t vdwxc_workspace_bytes(const int grid[3], vdwxc_precision precision) {
 vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
                               vdwxc_precision precision, int nq, const double* qmesh, int nk, double kmax,
                               const double* table, void* hip_stream) {
+  return vdwxc_init_table_ex(out, grid, cell, flavour, precision, nq, qmesh, nk, kmax, table, hip_stream, 0u);
+}
+
+vdwxc_status vdwxc_init_table_ex(vdwxc_handle* out, const int grid[3], const double cell[9], vdwxc_flavour flavour,
+                                 vdwxc_precision precision, int nq, const double* qmesh, int nk, double kmax,
+                                 const double* table, void* hip_stream, unsigned flags) {
   if (!out) return fail(nullptr, VDWXC_EINVAL, "out must not be NULL");
+  if (flags & ~unsigned(VDWXC_INIT_NO_WORKSPACE)) return fail(nullptr, VDWXC_EINVAL, "unknown init flags");
   *out = nullptr;
   vdwxc_status st = validate_common(grid, cell);
   if (st != VDWXC_OK) return st;
@@ -1195,13 +1209,17 @@ vdwxc_status vdwxc_init_table(vdwxc_handle* out, const int grid[3], const double
   h->buf_bytes = complex_buffer_bytes(h->n1, h->n2, h->n3, precision, nq);
   const Layout lay = workspace_layout(h->n1, h->n2, h->n3, precision, nq);
   h->ws_bytes = lay.total;
-  if ((e = hipMalloc(&h->d_ws, h->ws_bytes)) != hipSuccess) return bail(e, "work buffers");
-  h->work = carve(h->d_ws, lay);
+  if (!(flags & VDWXC_INIT_NO_WORKSPACE)) {
+    if ((e = hipMalloc(&h->d_ws, h->ws_bytes)) != hipSuccess) return bail(e, "work buffers");
+    h->work = carve(h->d_ws, lay);
+  }
   if ((e = hipMalloc(reinterpret_cast<void**>(&h->d_energy), sizeof(double))) != hipSuccess) return bail(e, "energy");
-  // flag [0]: raised by the theta pass, [1]: the last evaluation's result (see energy_reduce_block)
-  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, h->stream, h->work.flag);
-  if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(h->stream)) != hipSuccess)
-    return bail(e, "flag");
+  if (h->d_ws) {
+    // flag [0]: raised by the theta pass, [1]: the last evaluation's result (see energy_reduce_block)
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, h->stream, h->work.flag);
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+      return bail(e, "flag");
+  }
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&h->h_energy), sizeof(double), hipHostMallocDefault)) != hipSuccess)
     return bail(e, "pinned energy");
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&h->h_flag), sizeof(int), hipHostMallocDefault)) != hipSuccess)
@@ -1344,7 +1362,7 @@ vdwxc_status vdwxc_init(vdwxc_handle* out, const int grid[3], const double cell[
 
 vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double* sigma, double* dedn,
                                    double* dedsigma, double* energy_dev) {
-  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
   if (!n || !sigma || !dedn || !dedsigma || !energy_dev)
     return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
   return run_partials(h, h->work, n, sigma, dedn, dedsigma, energy_dev);
@@ -1352,7 +1370,7 @@ vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double
 
 vdwxc_status vdwxc_calculate(vdwxc_handle h, const double* n, const double* sigma, double* dedn, double* dedsigma,
                              double* energy_host) {
-  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
   if (!n || !sigma || !dedn || !dedsigma || !energy_host)
     return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
   vdwxc_status st = run_partials(h, h->work, n, sigma, dedn, dedsigma, h->d_energy);
@@ -1362,14 +1380,14 @@ vdwxc_status vdwxc_calculate(vdwxc_handle h, const double* n, const double* sigm
 
 vdwxc_status vdwxc_calculate_potential_async(vdwxc_handle h, const double* n, const double* grad_n, double* v,
                                              double* energy_dev) {
-  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
   if (!n || !v || !energy_dev) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
   return run_potential(h, h->work, n, grad_n, v, energy_dev);
 }
 
 vdwxc_status vdwxc_calculate_potential(vdwxc_handle h, const double* n, const double* grad_n, double* v,
                                        double* energy_host) {
-  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
   if (!n || !v || !energy_host) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
   vdwxc_status st = run_potential(h, h->work, n, grad_n, v, h->d_energy);
   if (st != VDWXC_OK) return st;
@@ -1395,10 +1413,29 @@ vdwxc_status vdwxc_calculate_potential_noalloc(vdwxc_handle h, const double* n, 
 }
 
 vdwxc_status vdwxc_calculate_lda_async(vdwxc_handle h, const double* n, double* v, double* energy_dev) {
-  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
   if (!n || !v || !energy_dev) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
   if (n == v) return fail(h, VDWXC_EINVAL, "v must not be the density array");
   return run_lda(h, h->work, n, v, energy_dev);
+}
+
+vdwxc_status vdwxc_set_workspace(vdwxc_handle h, void* workspace, size_t bytes) {
+  if (check_handle(h) != VDWXC_OK) return VDWXC_ESTATE;
+  const Layout lay = workspace_layout(h->n1, h->n2, h->n3, h->precision, h->M);
+  if (workspace) {
+    if (bytes < lay.total)
+      return fail(h, VDWXC_EINVAL, "workspace of " + std::to_string(bytes) + " bytes, the handle needs " +
+                                       std::to_string(lay.total));
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(h, VDWXC_EINVAL, "workspace must be 256-byte aligned");
+    h->work = carve(workspace, lay);
+  } else {
+    h->work = h->d_ws ? carve(h->d_ws, lay) : Work{};
+  }
+  if (!h->work.A) return VDWXC_OK;
+  HIP_TRY(h, hipSetDevice(h->device));
+  // the NaN flags live in the work memory and must start at zero
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, h->stream, h->work.flag);
+  return finish_launch(h);
 }
 
 const char* vdwxc_stage_name(int stage) {

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(PKG, "lib", "libvdwxc_gpu.so")
 OK, EINVAL, ENOMEM, EDEVICE, ETABLE, ESTATE = range(6)
 DF1, DF2 = 1, 2
 FP64, FP32_MIXED = 0, 1
+INIT_NO_WORKSPACE = 1
 FLAVOURS = {"DF1": DF1, "DF2": DF2, "vdW-DF1": DF1, "vdW-DF2": DF2}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED, "fp32_mixed": FP32_MIXED}
 
@@ -32,6 +33,9 @@ SIGNATURES = {
     "vdwxc_init": (ctypes.c_int, [ctypes.POINTER(_h), _ip, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_void_p]),
     "vdwxc_init_table": (ctypes.c_int, [ctypes.POINTER(_h), _ip, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                         ctypes.c_int, ctypes.c_double, _dp, ctypes.c_void_p]),
+    "vdwxc_init_table_ex": (ctypes.c_int, [ctypes.POINTER(_h), _ip, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                           ctypes.c_int, ctypes.c_double, _dp, ctypes.c_void_p, ctypes.c_uint]),
+    "vdwxc_set_workspace": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_size_t]),
     "vdwxc_calculate": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _dp]),
     "vdwxc_calculate_async": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]),
@@ -112,7 +116,8 @@ def _stream_handle(stream):
 class Functional:
     """A library handle for one grid, cell, flavour, precision and kernel table."""
 
-    def __init__(self, grid, cell, flavour="DF1", precision="fp64", table=None, stream=None, table_path=None):
+    def __init__(self, grid, cell, flavour="DF1", precision="fp64", table=None, stream=None, table_path=None,
+                 own_workspace: bool = True):
         import torch
         self.grid = tuple(int(x) for x in grid)
         self.cell = np.asarray(cell, dtype=np.float64).reshape(3, 3)
@@ -127,6 +132,8 @@ class Functional:
         g = (ctypes.c_int * 3)(*self.grid)
         fl = FLAVOURS[flavour] if isinstance(flavour, str) else int(flavour)
         pr = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if table_path is not None and not own_workspace:
+            raise ValueError("a handle without its own work memory takes the kernel table as arrays (table=...)")
         with torch.cuda.device(torch.cuda.current_device()):
             sh = _stream_handle(stream)
             if table_path is not None:
@@ -135,9 +142,9 @@ class Functional:
             else:
                 q = np.ascontiguousarray(table.qmesh, dtype=np.float64)
                 t = np.ascontiguousarray(table.table, dtype=np.float64)
-                st = L.vdwxc_init_table(ctypes.byref(self._h), g, _cell_array(self.cell), fl, pr, int(q.shape[0]),
-                                        q.ctypes.data_as(_dp), int(t.shape[0]), float(table.kmax),
-                                        t.ctypes.data_as(_dp), sh)
+                st = L.vdwxc_init_table_ex(ctypes.byref(self._h), g, _cell_array(self.cell), fl, pr, int(q.shape[0]),
+                                           q.ctypes.data_as(_dp), int(t.shape[0]), float(table.kmax),
+                                           t.ctypes.data_as(_dp), sh, 0 if own_workspace else INIT_NO_WORKSPACE)
         _check(st)
         self.nq = int(table.nq) if table is not None else None
 
@@ -220,6 +227,20 @@ class Functional:
         self.lda_async(n, v, e)
         torch.cuda.synchronize(n.device)
         return float(e.item()), v
+
+    def set_workspace(self, buf):
+        """Run later calls in `buf` (a CUDA tensor of at least workspace_bytes(grid, precision, nq)
+        bytes, kept alive by the caller while work enqueued with it is pending); None returns the
+        handle to its own work memory."""
+        self._sync_stream()
+        if buf is None:
+            st = lib().vdwxc_set_workspace(self._h, None, 0)
+        else:
+            if not buf.is_cuda or not buf.is_contiguous():
+                raise ValueError("workspace must be a contiguous CUDA tensor")
+            st = lib().vdwxc_set_workspace(self._h, ctypes.c_void_p(buf.data_ptr()),
+                                           buf.numel() * buf.element_size())
+        _check(st, self._h)
 
     def enable_timing(self, enable: bool = True):
         """Record HIP events around every kernel launch of this handle (see read_timing)."""

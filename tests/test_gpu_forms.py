@@ -180,8 +180,9 @@ def test_serving_admission_under_small_budget(dev):
 
 
 def test_serving_warm_handles(dev):
-    """Handles created ahead of traffic: every slot gets one per shape while the budget lasts,
-    the budget is never exceeded, no request creates another, and the results are the same bits."""
+    """Handles (which own no work memory) and the buffer pool created ahead of traffic: every slot
+    gets one handle per shape, no request creates another or allocates a buffer, the pool stays
+    within the budget, and the results are the same bits."""
     from paper_1703_06999_amd import serving, vdwxc
     say("[serving warm]")
     reqs = _small_requests(12, rate=3000.0, seed=4, grids=(16, 24))
@@ -190,19 +191,48 @@ def test_serving_warm_handles(dev):
     assert srv.warm(shapes) == 6
     assert srv.warm(shapes) == 0                       # already resident
     before = {s.index: set(s.handles) for s in srv.slots}
+    pool = [(b.size, b.mem.data_ptr()) for b in srv.buffers]
     summary = srv.run(reqs)
     assert {s.index: set(s.handles) for s in srv.slots} == before
+    assert [(b.size, b.mem.data_ptr()) for b in srv.buffers] == pool
     srv.close()
     say(f"    {summary}")
     assert summary["requests"] == len(reqs)
     for r in reqs:
         E, v = _alone(r, "fp32")
         assert float(r.energy.item()) == E and torch.equal(r.v, v), r.rid
-    small = serving.Server(KT, slots=3, precision="fp32",
-                           hbm_budget=2.5 * vdwxc.workspace_bytes((24, 24, 24), "fp32", KT.nq))
-    made = small.warm(shapes)
-    assert 1 <= made < 6 and small.peak_resident <= small.budget
+    w16, w24 = (vdwxc.workspace_bytes((g, g, g), "fp32", KT.nq) for g in (16, 24))
+    small = serving.Server(KT, slots=3, precision="fp32", hbm_budget=2.5 * w24)
+    assert small.warm(shapes) == 6
+    # greedy size classes: two 24^3 buffers, then the 16^3 class in the remaining half
+    assert [b.size for b in small.buffers] == [w24, w24, w16] and small.peak_resident <= small.budget
     small.close()
+
+
+def test_serving_pool_under_small_budget(dev):
+    """Warmed pool under a budget of one large and a few small buffers: large requests queue for the
+    large buffer while small ones keep running in the small buffers (never taking the buffer a
+    waiting large request needs), nothing is allocated after warm-up, and every result is the
+    request's own bits."""
+    from paper_1703_06999_amd import serving, vdwxc
+    say("[serving pool]")
+    reqs = _small_requests(16, rate=4000.0, seed=8, grids=(16, 24, 32))
+    shapes = [((g, g, g), inputs.cubic_cell(g * 0.3)) for g in (16, 24, 32)]
+    w = {g: vdwxc.workspace_bytes((g, g, g), "fp32", KT.nq) for g in (16, 24, 32)}
+    srv = serving.Server(KT, slots=4, precision="fp32", hbm_budget=w[32] + w[24] + 1.5 * w[16])
+    srv.warm(shapes)
+    assert [b.size for b in srv.buffers] == [w[32], w[24], w[16]]
+    pool = [b.mem.data_ptr() for b in srv.buffers]
+    summary = srv.run(reqs)
+    say(f"    {summary}")
+    assert [b.mem.data_ptr() for b in srv.buffers] == pool
+    assert summary["requests"] == len(reqs) and summary["max_concurrent"] >= 2
+    for r in reqs:
+        assert srv.buffers[r.buffer].size >= w[r.grid[0]]
+    srv.close()
+    for r in reqs:
+        E, v = _alone(r, "fp32")
+        assert float(r.energy.item()) == E and torch.equal(r.v, v), r.rid
 
 
 def test_serving_results_match_oracle(dev):

@@ -93,3 +93,14 @@ def test_stage_bytes_model():
     assert bench.stage_bytes("y_fwd", g, "fp64") == 2 * 20 * Nk * 16
     assert bench.stage_bytes("div_y", g, "fp32") == 5 * 4 * N
     assert bench.stage_bytes("no_such_stage", g, "fp32") == 0.0
+
+
+def test_serving_pool_plan_is_greedy_by_size_class():
+    """The server's buffer pool: repeatedly the largest work-memory class that still fits the
+    budget, at most one buffer per slot."""
+    from paper_1703_06999_amd.serving import plan_pool
+    w = {g: g ** 3 for g in (48, 64, 96, 128, 160)}
+    assert plan_pool(w.values(), 1.25 * w[160], 4) == [w[160], w[96], w[48]]
+    assert plan_pool(w.values(), 64 * w[160], 4) == [w[160]] * 4
+    assert plan_pool(w.values(), 0.5 * w[48], 4) == []
+    assert plan_pool([w[64], w[64]], 10 * w[64], 3) == [w[64]] * 3
