@@ -435,8 +435,9 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
 // no per-point state in LDS (the block holds the ty lines, the twiddles and the spline tables,
 // half the LDS of the general kernel) and no theta round trip through LDS.  nthr = 64 ty.  WPE:
 // the waves per SIMD the registers must allow (the eight points' state in FP64 needs more than
-// the 128 registers of four).
-template <typename T, bool SIGMA_FROM_GRAD, int WPE>
+// the 128 registers of four).  PB field pairs go through one transform (PB ty lines in LDS): fewer
+// rounds of transform, store and barrier per block.
+template <typename T, bool SIGMA_FROM_GRAD, int WPE, int PB>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
                 typename Cx<T>::type* __restrict__ A, Quad<T>* __restrict__ state, int* __restrict__ flag,
@@ -453,7 +454,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
   const int y0 = tile * ty, M = g.M;
   const size_t N = size_t(g.n1) * g.n2 * n3;
   T2* line = reinterpret_cast<T2*>(smem);
-  const SplineLds<T> S = load_spline_lds<T>(smem, size_t(ty) * lstride * sizeof(T2), qmesh, mm, M, tid, nthr);
+  const SplineLds<T> S = load_spline_lds<T>(smem, size_t(PB) * ty * lstride * sizeof(T2), qmesh, mm, M, tid, nthr);
   // the thread's points
   const int yl = __builtin_amdgcn_readfirstlane(tid >> 6), i = tid & 63, y = y0 + yl;
   const bool live = y < g.n2;
@@ -489,13 +490,15 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
   const int npairs = (M + 1) >> 1;
   const size_t kzstride = size_t(g.n1) * g.n2, fstride = size_t(g.h3) * kzstride;
 #pragma unroll 1
-  for (int pr = 0; pr < npairs; ++pr) {
-    const int fa = 2 * pr, fb = 2 * pr + 1;
+  for (int pr0 = 0; pr0 < npairs; pr0 += PB) {
+    const int nb = min(PB, npairs - pr0);
     // theta_a = n p_a = n [u d_ab + t d_a,b+1 + c6 ((u^3-u) m_b,a + (t^3-t) m_b+1,a)] of fields fa,
-    // fa+1 as the real and imaginary part of the first stage's input
-    lds_fft512<1, -1, kLdsPadShift>(
-        line, ty, lstride, twl, tid, nthr,
-        [&](int, int r, int) {
+    // fa+1 as the real and imaginary part of the first stage's input (line l = yl + q ty holds
+    // pair pr0 + q)
+    lds_fft512<PB, -1, kLdsPadShift>(
+        line, nb * ty, lstride, twl, tid, nthr,
+        [&](int l, int r, int) {
+          const int fa = 2 * (pr0 + (l - yl) / ty), fb = fa + 1;
           const int b = pb[r];
           T ta = T(0), tb = T(0);
           if (b != 255) {
@@ -512,20 +515,24 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
         },
         LdsLines{});
     // A[f][kz][x][y0 + yl] = Aa[kz * kzstride + yl] (field fa), Aa[fstride + ...] (field fb)
-    T2* Aa = A + a_index(g, fa, 0, x, y0);
-    const int nout = ty * g.h3;
-    DivModStep ot(tid, nthr, ty);
+    for (int q = 0; q < nb; ++q) {
+      const int fa = 2 * (pr0 + q), fb = fa + 1;
+      T2* Aa = A + a_index(g, fa, 0, x, y0);
+      const T2* lq = line + size_t(q) * ty * lstride;
+      const int nout = ty * g.h3;
+      DivModStep ot(tid, nthr, ty);
 #pragma unroll 1
-    for (int e = tid; e < nout; e += nthr, ot.next()) {
-      const int ol = ot.r, kz = ot.q;
-      if (y0 + ol < g.n2) {
-        const T2 zk = line[ol * lstride + lidx<>(kz)];
-        const T2 zn = line[ol * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
-        T2 xa, xb;
-        split_pair(zk, zn, xa, xb);
-        T2* dst = Aa + size_t(kz) * kzstride + ol;
-        dst[0] = xa;
-        if (fb < M) dst[fstride] = xb;
+      for (int e = tid; e < nout; e += nthr, ot.next()) {
+        const int ol = ot.r, kz = ot.q;
+        if (y0 + ol < g.n2) {
+          const T2 zk = lq[ol * lstride + lidx<>(kz)];
+          const T2 zn = lq[ol * lstride + lidx<>(kz == 0 ? 0 : n3 - kz)];
+          T2 xa, xb;
+          split_pair(zk, zn, xa, xb);
+          T2* dst = Aa + size_t(kz) * kzstride + ol;
+          dst[0] = xa;
+          if (fb < M) dst[fstride] = xb;
+        }
       }
     }
     __syncthreads();

@@ -45,6 +45,11 @@ namespace {
 #endif
 template <typename T>
 constexpr int t512_wpe() { return sizeof(T) == 8 ? VDWXC_T512_WPE64 : 4; }
+#ifndef VDWXC_T512_PB64
+#define VDWXC_T512_PB64 2
+#endif
+template <typename T>
+constexpr int t512_pb() { return sizeof(T) == 8 ? VDWXC_T512_PB64 : 1; }
 // the register-state assembly for N3 = 512 (k_zinv_assemble512): lines per block, field pairs per
 // transform and waves per SIMD, per precision
 #ifndef VDWXC_A512_TILE64
@@ -907,10 +912,10 @@ void enqueue_main(vdwxc_ctx* h, const Work& w, const double* n, const double* si
     const Launch& L5 = Prec<T>::z512(h);
     const dim3 g5((h->n2 + L5.tile - 1) / L5.tile, h->n1);
     if (sig_from_grad)
-      hipLaunchKernelGGL((k_theta_zfwd512<T, true, t512_wpe<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.flag,
+      hipLaunchKernelGGL((k_theta_zfwd512<T, true, t512_wpe<T>(), t512_pb<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.flag,
                          tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride);
     else
-      hipLaunchKernelGGL((k_theta_zfwd512<T, false, t512_wpe<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.flag,
+      hipLaunchKernelGGL((k_theta_zfwd512<T, false, t512_wpe<T>(), t512_pb<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.flag,
                          tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride);
   } else if (sig_from_grad) {
     hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, true>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A, state,
@@ -1276,10 +1281,11 @@ vdwxc_status vdwxc_init_table_ex(vdwxc_handle* out, const int grid[3], const dou
   if (h->z512) {
     for (Launch* L : {&h->t512_64, &h->t512_32}) {
       const size_t cplx = L == &h->t512_64 ? 16 : 8;
+      const int pb = cplx == 16 ? t512_pb<double>() : t512_pb<float>();
       L->tile = std::min(cplx == 16 ? VDWXC_T512_TILE64 : VDWXC_T512_TILE32, h->n2);
       L->nthr = 64 * L->tile;
       L->lstride = lds_span<>(512);
-      L->lds = tw_lds_bytes<double2>(512) * cplx / 16 + size_t(L->tile) * L->lstride * cplx +
+      L->lds = tw_lds_bytes<double2>(512) * cplx / 16 + size_t(pb) * L->tile * L->lstride * cplx +
                (cplx == 16 ? spline_lds_bytes<double>() : spline_lds_bytes<float>()) + 16;
     }
     for (Launch* L : {&h->a512_64, &h->a512_32}) {
@@ -1295,10 +1301,10 @@ vdwxc_status vdwxc_init_table_ex(vdwxc_handle* out, const int grid[3], const dou
     }
     set_lds_limit(k_zinv_assemble512<double, a512_pb<double>(), a512_wpe<double>(), a512_pf<double>()>, h->a512_64.lds);
     set_lds_limit(k_zinv_assemble512<float, a512_pb<float>(), a512_wpe<float>(), a512_pf<float>()>, h->a512_32.lds);
-    set_lds_limit(k_theta_zfwd512<double, true, t512_wpe<double>()>, h->t512_64.lds);
-    set_lds_limit(k_theta_zfwd512<double, false, t512_wpe<double>()>, h->t512_64.lds);
-    set_lds_limit(k_theta_zfwd512<float, true, t512_wpe<float>()>, h->t512_32.lds);
-    set_lds_limit(k_theta_zfwd512<float, false, t512_wpe<float>()>, h->t512_32.lds);
+    set_lds_limit(k_theta_zfwd512<double, true, t512_wpe<double>(), t512_pb<double>()>, h->t512_64.lds);
+    set_lds_limit(k_theta_zfwd512<double, false, t512_wpe<double>(), t512_pb<double>()>, h->t512_64.lds);
+    set_lds_limit(k_theta_zfwd512<float, true, t512_wpe<float>(), t512_pb<float>()>, h->t512_32.lds);
+    set_lds_limit(k_theta_zfwd512<float, false, t512_wpe<float>(), t512_pb<float>()>, h->t512_32.lds);
   }
 
   // dynamic LDS above the default limit
