@@ -48,8 +48,11 @@ constexpr int t512_wpe() { return sizeof(T) == 8 ? VDWXC_T512_WPE64 : 4; }
 #ifndef VDWXC_T512_PB64
 #define VDWXC_T512_PB64 2
 #endif
+#ifndef VDWXC_T512_PB32
+#define VDWXC_T512_PB32 1
+#endif
 template <typename T>
-constexpr int t512_pb() { return sizeof(T) == 8 ? VDWXC_T512_PB64 : 1; }
+constexpr int t512_pb() { return sizeof(T) == 8 ? VDWXC_T512_PB64 : VDWXC_T512_PB32; }
 // the register-state assembly for N3 = 512 (k_zinv_assemble512): lines per block, field pairs per
 // transform and waves per SIMD, per precision
 #ifndef VDWXC_A512_TILE64
