@@ -82,6 +82,7 @@ def stage_bytes(stage: str, grid, precision: str, m: int = M) -> float:
         "div_z": 32 * N + 3 * r * N,                  # S + grad in; A, B1, B2 out
         "div_y": 5 * r * N,                            # A, B1, B2 in; A', B1' out
         "div_x": 2 * r * N + 16 * N,                   # A', B1' and v in; v out
+        "lda": 16 * N,                                 # n in, v_c^LDA out (FP64 in both forms)
     }.get(stage, 0.0)
 
 

@@ -31,7 +31,7 @@ KERNEL_SOURCES = ["paper_1703_06999_amd/csrc/kernels.h", "paper_1703_06999_amd/c
 _STAGE_ORDER = [
     ("k_theta_zfwd", "theta_zfwd"), ("k_ypass_fwd", "y_fwd"), ("k_xcontract", "x_contract"),
     ("k_ypass_inv", "y_inv"), ("k_zinv_assemble", "z_assemble"),
-    ("k_div_z", "div_z"), ("k_div_y", "div_y"), ("k_div_x", "div_x"),
+    ("k_div_z", "div_z"), ("k_div_y", "div_y"), ("k_div_x", "div_x"), ("k_lda_pw92", "lda"),
 ]
 
 
