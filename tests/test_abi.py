@@ -160,5 +160,22 @@ def test_null_handle_calls():
     assert L.vdwxc_calculate_potential(None, None, None, None, ctypes.byref(e)) == vdwxc.ESTATE
     assert L.vdwxc_print(None) == vdwxc.ESTATE
     assert L.vdwxc_set_stream(None, None) == vdwxc.ESTATE
+    assert L.vdwxc_calculate_lda_async(None, None, None, None) == vdwxc.ESTATE
+    assert L.vdwxc_calculate_potential_noalloc(None, None, None, None, None) == vdwxc.ESTATE
+    assert L.vdwxc_set_workspace(None, None, 0) == vdwxc.ESTATE
     h = ctypes.c_void_p()
     assert L.vdwxc_finalize(ctypes.byref(h)) == vdwxc.ESTATE
+
+
+def test_init_ex_rejects_unknown_flags():
+    """vdwxc_init_table_ex checks its flags before any device work (no GPU needed here)."""
+    L = vdwxc.lib()
+    h = ctypes.c_void_p()
+    g = (ctypes.c_int * 3)(4, 4, 4)
+    c = (ctypes.c_double * 9)(*(np.eye(3) * 5).ravel().tolist())
+    q = np.ascontiguousarray(KT.qmesh)
+    t = np.ascontiguousarray(KT.table)
+    st = L.vdwxc_init_table_ex(ctypes.byref(h), g, c, 1, 0, len(q), q.ctypes.data_as(vdwxc._dp), t.shape[0],
+                               KT.kmax, t.ctypes.data_as(vdwxc._dp), None, 2)
+    assert st == vdwxc.EINVAL and not h.value
+    assert "flags" in L.vdwxc_last_error(None).decode()
