@@ -346,6 +346,23 @@ __device__ __forceinline__ void lds_fft_stages(T2* buf, const AxisPlan& plan, in
 // the thread's 8 per line).  64 consecutive threads access 64 consecutive elements of one line.
 struct LdsLines {};
 
+// Order a wave's own LDS accesses across this point (its earlier reads and writes complete before
+// its later ones), without waiting for the other waves of the block.  WAVE = 0: a block barrier.
+#ifndef VDWXC_FFT512_WAVESYNC
+#define VDWXC_FFT512_WAVESYNC 1
+#endif
+template <int WAVE>
+__device__ __forceinline__ void wave_lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the wave's LDS operations have completed
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int MAXB, int DIR, int PS, typename T2, typename In = LdsLines, typename Out = LdsLines>
 __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, const T2* __restrict__ tw, int tid,
                                            int nthr, In in = In{}, Out out = Out{}) {
@@ -414,7 +431,9 @@ __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, con
         }
       }
     } else {
-      __syncthreads();
+      // every line is read and written by one wave only (lines l0 + c lstep), so between stages
+      // the wave orders its own LDS accesses; the block synchronises only after the last stage
+      wave_lds_sync<VDWXC_FFT512_WAVESYNC>();
       int wo[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r)
@@ -429,7 +448,8 @@ __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, con
         }
       }
     }
-    __syncthreads();   // (after the last stage: the caller may reuse the LDS lines)
+    if (s == 2) __syncthreads();   // the caller reads the lines with its own mapping, or reuses them
+    else wave_lds_sync<VDWXC_FFT512_WAVESYNC>();
   }
 }
 
