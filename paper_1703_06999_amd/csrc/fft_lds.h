@@ -363,7 +363,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   }
 }
 
-template <int MAXB, int DIR, int PS, typename T2, typename In = LdsLines, typename Out = LdsLines>
+// END_SYNC: end with a block barrier (the caller then may read or reuse every line); without it
+// (only with an output functor) the caller orders later LDS use itself.
+template <int MAXB, int DIR, int PS, bool END_SYNC = true, typename T2, typename In = LdsLines, typename Out = LdsLines>
 __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, const T2* __restrict__ tw, int tid,
                                            int nthr, In in = In{}, Out out = Out{}) {
   constexpr bool kInLds = std::is_same<In, LdsLines>::value, kOutLds = std::is_same<Out, LdsLines>::value;
@@ -432,7 +434,8 @@ __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, con
       }
     } else {
       // every line is read and written by one wave only (lines l0 + c lstep), so between stages
-      // the wave orders its own LDS accesses; the block synchronises only after the last stage
+      // the wave orders its own LDS accesses; the block synchronises only after the last stage.
+      // (Twiddles in LDS must therefore be complete before the call: the caller's barrier.)
       wave_lds_sync<VDWXC_FFT512_WAVESYNC>();
       int wo[8];
 #pragma unroll
@@ -448,8 +451,8 @@ __device__ __forceinline__ void lds_fft512(T2* buf, int nlines, int lstride, con
         }
       }
     }
-    if (s == 2) __syncthreads();   // the caller reads the lines with its own mapping, or reuses them
-    else wave_lds_sync<VDWXC_FFT512_WAVESYNC>();
+    if (s < 2) wave_lds_sync<VDWXC_FFT512_WAVESYNC>();
+    else if (END_SYNC || kOutLds) __syncthreads();   // the caller reads the lines with its own mapping, or reuses them
   }
 }
 

@@ -549,7 +549,6 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
   using T2 = typename Cx<T>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   unsigned char* smem = smem_raw + tw_lds_bytes<T2>(g.n2);
-  const T2* twl = stage_twiddles(smem_raw, tw, g.n2, threadIdx.x, blockDim.x);
   T2* line = reinterpret_cast<T2*>(smem);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int nb = gridDim.x * gridDim.y * gridDim.z;
@@ -559,7 +558,11 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
   // 512-point lines: the first forward stage reads the A lines (y contiguous) straight from global
   // memory, the last inverse stage writes them there
   const bool f512 = n2 == 512 && (nthr & 63) == 0;
+  const T2* twl = stage_twiddles(smem_raw, tw, g.n2, tid, nthr);
   if (DIR < 0 && f512) {
+    // the staged twiddles are read from the second stage on, and the transform synchronises its
+    // stages within each wave only
+    __syncthreads();
     const T2* sbase = src + a_index(g, f, kz, x0, 0);
     lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift>(
         line, tx, lstride, twl, tid, nthr,
@@ -582,10 +585,10 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
   if (DIR > 0 && f512) {
     __syncthreads();
     T2* dbase = dst + a_index(g, f, kz, x0, 0);
-    lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift>(line, tx, lstride, twl, tid, nthr, LdsLines{},
-                                                [&](int xl, int, int y, T2 v) {
-                                                  if (x0 + xl < g.n1) dbase[size_t(xl) * 512 + y] = v;
-                                                });
+    lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift, false>(line, tx, lstride, twl, tid, nthr, LdsLines{},
+                                                       [&](int xl, int, int y, T2 v) {
+                                                         if (x0 + xl < g.n1) dbase[size_t(xl) * 512 + y] = v;
+                                                       });
     return;
   }
   if (!(DIR < 0 && f512)) {
@@ -948,8 +951,8 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
   if (f512) {
     // 512-point columns: the last inverse stage stores straight to global memory (no LDS round
     // trip and barrier; it also frees registers: 18.4 -> 17.4 ms FP64, 11.1 -> 9.7 ms FP32 at 512^3)
-    lds_fft512<(EPT + 7) / 8, +1, PS>(line, M, ls, twl, tid, nthr, LdsLines{},
-                                      [&](int f, int, int x, T2 v) { cb[size_t(f) * fstride + x] = v; });
+    lds_fft512<(EPT + 7) / 8, +1, PS, false>(line, M, ls, twl, tid, nthr, LdsLines{},
+                                             [&](int f, int, int x, T2 v) { cb[size_t(f) * fstride + x] = v; });
   } else {
     for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1, PS>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
     DivModStep it(tid, nthr, n1);
