@@ -115,14 +115,23 @@ constexpr int kMaxThreadsY = 1024; // y passes
 constexpr int kMaxThreadsX = 512;  // x passes: one thread per contraction slot
 constexpr int kLineTile = 16;    // lines per block in the z and y passes
 // Lines per block of the y passes.  Measured at 512^3: 8-line FP64 blocks (74 KB of LDS, two per
-// CU) beat 16-line ones (139 KB, one per CU) by 19 % (forward) and 28 % (inverse); in FP32 the
-// forward pass keeps 16 lines, whose transposed writes are then whole 128-byte rows (8 lines:
-// +9 %), and the inverse takes 8 (-7 %).  4-line blocks are slower in both precisions.
+// CU) beat 16-line ones (139 KB, one per CU) by 19 % (forward) and 28 % (inverse) while the
+// 512-point transform synchronised its stages over the block; with stages synchronised within each
+// wave, the 512-point forward pass takes 16 lines (8.1 -> 7.2 ms), the inverse keeps 8 (16 lines:
+// 8.2 -> 8.8 ms).  In FP32 the forward pass keeps 16 lines, whose transposed writes are then whole
+// 128-byte rows (8 lines: +9 %), and the inverse takes 8 (-7 %).  4-line blocks are slower in both
+// precisions.
 #ifndef VDWXC_YTILE64
 #define VDWXC_YTILE64 8
 #endif
+#ifndef VDWXC_YTILE64_512
+#define VDWXC_YTILE64_512 16
+#endif
 #ifndef VDWXC_YTILE32
 #define VDWXC_YTILE32 16
+#endif
+#ifndef VDWXC_YTILE64_INV
+#define VDWXC_YTILE64_INV 8
 #endif
 #ifndef VDWXC_YTILE32_INV
 #define VDWXC_YTILE32_INV 8
@@ -273,7 +282,7 @@ struct vdwxc_ctx {
   int device = 0;
   Geometry geo{};
   AxisPlan plan[3]{};
-  Launch zl64, zl32, za64, za32, yl64, yl32, yl32i, xl64, xl32;
+  Launch zl64, zl32, za64, za32, yl64, yl64i, yl32, yl32i, xl64, xl32;
   Launch dz64, dz32, dy64, dy32, dx64, dx32;   // divergence passes (lds: the whole block)
   Launch gz, gy, gx;                           // gradient passes, FP64 (lds: the whole block)
   size_t lds_theta64 = 0, lds_theta32 = 0, lds_asm64 = 0, lds_asm32 = 0;
@@ -766,7 +775,7 @@ template <> struct Prec<double> {
   static const Launch& za(const vdwxc_ctx* h) { return h->za64; }
   static const Launch& z512(const vdwxc_ctx* h) { return h->t512_64; }
   static const Launch& a512(const vdwxc_ctx* h) { return h->a512_64; }
-  static const Launch& y(const vdwxc_ctx* h, int) { return h->yl64; }
+  static const Launch& y(const vdwxc_ctx* h, int dir) { return dir < 0 ? h->yl64 : h->yl64i; }
   static const Launch& x(const vdwxc_ctx* h) { return h->xl64; }
   static const Launch& div(const vdwxc_ctx* h, int a) { return a == 2 ? h->dz64 : a == 1 ? h->dy64 : h->dx64; }
   static const double2* tw(const vdwxc_ctx* h, int a) { return h->tw[a]->d64; }
@@ -1152,7 +1161,8 @@ vdwxc_status vdwxc_init_table_ex(vdwxc_handle* out, const int grid[3], const dou
     return fail(nullptr, VDWXC_EINVAL, "grid reaches |G| >= kmax of the kernel table (grid too fine)");
   }
   bool ok = line_launch(kMaxThreadsZ, h->n3, h->n2, 16, h->zl64) && line_launch(kMaxThreadsZ, h->n3, h->n2, 8, h->zl32) &&
-            line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64, kEPT, VDWXC_YTILE64) &&
+            line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64, kEPT, h->n2 == 512 ? VDWXC_YTILE64_512 : VDWXC_YTILE64) &&
+            line_launch(kMaxThreadsY, h->n2, h->n1, 16, h->yl64i, kEPT, VDWXC_YTILE64_INV) &&
             line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32, kEPT, VDWXC_YTILE32) &&
             line_launch(kMaxThreadsY, h->n2, h->n1, 8, h->yl32i, kEPT, VDWXC_YTILE32_INV);
   {
@@ -1318,7 +1328,7 @@ vdwxc_status vdwxc_init_table_ex(vdwxc_handle* out, const int grid[3], const dou
   set_lds_limit(k_zinv_assemble<double, kEPTA, kEPTA, asm_pb<double>()>, h->lds_asm64);
   set_lds_limit(k_zinv_assemble<float, kEPTA, kEPTA, asm_pb<float>()>, h->lds_asm32);
   set_lds_limit(k_ypass<double, kEPT, -1>, h->yl64.lds);
-  set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64.lds);
+  set_lds_limit(k_ypass<double, kEPT, +1>, h->yl64i.lds);
   set_lds_limit(k_ypass<float, kEPT, -1>, h->yl32.lds);
   set_lds_limit(k_ypass<float, kEPT, +1>, h->yl32i.lds);
   switch (q_bucket(nq)) {
