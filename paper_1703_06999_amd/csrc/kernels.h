@@ -4,10 +4,10 @@
 // Data layout in HBM (N1 x N2 x N3 grid, N3 contiguous, H = N3/2 + 1, f = field index alpha):
 //   n, sigma, dedn, dedsigma, v : double [N1][N2][N3]
 //   A (z-transformed)           : complex [f][kz][x][y]      (y contiguous)
-//   B (z,y-transformed)         : complex [f][ky][kz][x]     (x contiguous)
-// Each FFT pass transforms the contiguous axis of its input and writes the transformed axis to
-// the slowest position, so every global access is a contiguous run (a line, or a tile row of 16
-// elements).  The x pass is done in place in B and carries the k-space contraction between its
+//   B (z,y-transformed)         : complex [f][kz][ky][x]     (x contiguous)
+// Each FFT pass transforms the contiguous axis of its input and writes the transformed axis out
+// of the contiguous position, so every global access is a contiguous run (a line, or a tile row
+// of 16 elements).  The x pass is done in place in B and carries the k-space contraction between its
 // forward and inverse transforms.  Real fields are transformed two at a time as the real and
 // imaginary part of one complex line.
 #pragma once
@@ -123,8 +123,11 @@ __device__ __forceinline__ void q0_state(double n, double sigma, double zab, con
 __device__ __forceinline__ size_t a_index(const Geometry& g, int f, int kz, int x, int y) {
   return ((size_t(f) * g.h3 + kz) * g.n1 + x) * g.n2 + y;
 }
+// B: [f][kz][ky][x].  With ky inside kz, the rows a y-pass block writes (one per ky, for its kz
+// and x tile) lie in one N2*N1 window of a field instead of N1*H apart, which keeps the pass's
+// address translations few
 __device__ __forceinline__ size_t b_index(const Geometry& g, int f, int ky, int kz, int x) {
-  return ((size_t(f) * g.n2 + ky) * g.h3 + kz) * g.n1 + x;
+  return ((size_t(f) * g.h3 + kz) * g.n2 + ky) * g.n1 + x;
 }
 
 // Split the z-spectrum Z = FFT(a + i b) of two real lines into their half spectra at index k:
@@ -539,7 +542,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
   }
 }
 
-// ---- pass 2 / 4: y FFT with rotation A[f][kz][x][y] <-> B[f][ky][kz][x] ----------------------
+// ---- pass 2 / 4: y FFT with rotation A[f][kz][x][y] <-> B[f][kz][ky][x] ----------------------
 // Block: TX consecutive x of one (f, kz) (blockIdx.x = x tile, .y = kz, .z = f).
 
 template <typename T, int EPT, int DIR>
@@ -574,9 +577,9 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
         tid, nthr, tot, n2, [&](int e, int xl, int) { return (x0 + xl < g.n1) ? sbase[e] : T2{T(0), T(0)}; },
         [&](int, int xl, int y, T2 v) { line[xl * lstride + lidx<>(y)] = v; });
   } else {
-    // B[f][ky][kz][x0 + xl] = sbase[size_t(ky) * ystride + xl]
+    // B[f][kz][ky][x0 + xl] = sbase[size_t(ky) * ystride + xl]
     const T2* sbase = src + b_index(g, f, 0, kz, x0);
-    const int ystride = g.h3 * g.n1;
+    const int ystride = g.n1;
     gather_strided_dm<8>(
         tid, nthr, tot, tx,
         [&](int, int ky, int xl) { return (x0 + xl < g.n1) ? sbase[size_t(ky) * ystride + xl] : T2{T(0), T(0)}; },
@@ -597,7 +600,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
   }
   if (DIR < 0) {
     T2* dbase = dst + b_index(g, f, 0, kz, x0);
-    const int ystride = g.h3 * g.n1;
+    const int ystride = g.n1;
     DivModStep it(tid, nthr, tx);
     for (int e = tid; e < tot; e += nthr, it.next()) {
       const int xl = it.r, ky = it.q;
@@ -633,9 +636,9 @@ __device__ __forceinline__ double gnorm2(const Geometry& g, int kx, int ky, int 
 }
 
 // ---- pass 3: x FFT, k-space contraction, inverse x FFT (in place in B) -----------------------
-// Block: the M field lines of one (ky, kz) column (blockIdx.x = kz, .y = ky).  With kz fastest,
+// Block: the M field lines of one (ky, kz) column (blockIdx.x = ky, .y = kz).  With ky fastest,
 // the blocks resident at one time read and write one contiguous window of each field (the lines
-// of consecutive kz are adjacent in B) instead of lines a whole kz-plane apart.
+// of consecutive ky are adjacent in B) instead of lines a whole plane apart.
 // Per k: phi_ab = (1-w) T_j,ab + w T_j+1,ab with |G| = (j + w) dk (Sec. 3 step 3a);
 // F_a = sum_b phi_ab theta_b (step 3b); energy sum_a Re theta_a* F_a (step 3c), weight 2 for kz
 // strictly inside the half spectrum, 1 on its edges.  phi is symmetric, so each unordered pair
@@ -776,7 +779,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
   const T2* twl = tw;                       // twiddles from global memory (L1/L2 resident)
   T2* line = reinterpret_cast<T2*>(smem);   // all M field lines of the column
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int kz = blockIdx.x, ky = blockIdx.y, M = g.M, n1 = g.n1;
+  const int ky = blockIdx.x, kz = blockIdx.y, M = g.M, n1 = g.n1;
   const int ls = lds_span<PS>(n1);
   // field f of this column: cb[f * fstride + x]
   T2* cb = B + b_index(g, 0, ky, kz, 0);

@@ -151,7 +151,7 @@ struct Launch {
 // the allocation-free path, where taking an event could allocate).
 struct Work {
   void* A = nullptr;           // complex [f][kz][x][y] (z pass output), real fields of the div/grad passes
-  void* B = nullptr;           // complex [f][ky][kz][x] (y pass output)
+  void* B = nullptr;           // complex [f][kz][ky][x] (y pass output)
   double* S = nullptr;         // dE/dsigma of the potential entry [N]
   void* state = nullptr;       // per-point spline state Quad<T> [N], theta pass -> assembly
   double* G = nullptr;         // spectral gradient [3][N]
@@ -889,12 +889,12 @@ void launch_xcontract(vdwxc_ctx* h, const Work& w, typename Cx<T>::type* B) {
   const Launch& Lx = Prec<T>::x(h);
   if constexpr (sizeof(T) == 4) {
     if (h->x_capped) {
-      hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 4, MB>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream,
+      hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 4, MB>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream,
                          B, Prec<T>::table(h), w.partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
       return;
     }
   }
-  hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 1, MB>), dim3(h->h3, h->n2), dim3(Lx.nthr), Lx.lds, h->stream, B,
+  hipLaunchKernelGGL((k_xcontract<T, kEPTC, kXPad, 1, MB>), dim3(h->n2, h->h3), dim3(Lx.nthr), Lx.lds, h->stream, B,
                      Prec<T>::table(h), w.partials, Prec<T>::tw(h, 0), h->geo, h->plan[0]);
 }
 
