@@ -3,7 +3,7 @@
 //
 // Data layout in HBM (N1 x N2 x N3 grid, N3 contiguous, H = N3/2 + 1, f = field index alpha):
 //   n, sigma, dedn, dedsigma, v : double [N1][N2][N3]
-//   A (z-transformed)           : complex [f][kz][x][y]      (y contiguous)
+//   A (z-transformed)           : complex [f][x][kz][y]      (y contiguous)
 //   B (z,y-transformed)         : complex [f][kz][ky][x]     (x contiguous)
 // Each FFT pass transforms the contiguous axis of its input and writes the transformed axis out
 // of the contiguous position, so every global access is a contiguous run (a line, or a tile row
@@ -120,8 +120,10 @@ __device__ __forceinline__ void q0_state(double n, double sigma, double zab, con
   t = (q0 - q[b]) / (q[b + 1] - q[b]);
 }
 
+// A: [f][x][kz][y].  A z-pass block (one x, a tile of y) then writes and reads rows that lie in one
+// H*N2 window of a field instead of N1*N2 apart, which keeps its address translations few
 __device__ __forceinline__ size_t a_index(const Geometry& g, int f, int kz, int x, int y) {
-  return ((size_t(f) * g.h3 + kz) * g.n1 + x) * g.n2 + y;
+  return ((size_t(f) * g.n1 + x) * g.h3 + kz) * g.n2 + y;
 }
 // B: [f][kz][ky][x].  With ky inside kz, the rows a y-pass block writes (one per ky, for its kz
 // and x tile) lie in one N2*N1 window of a field instead of N1*H apart, which keeps the pass's
@@ -410,9 +412,9 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
     __syncthreads();
     lds_fft<EPT, -1>(line, zp, ty, lstride, twl, tid, nthr);
     const int nout = ty * g.h3;
-    // A[f][kz][x][y0 + yl] = Aa[kz * kzstride + yl] (field fa), Aa[fstride + ...] (field fb)
+    // A[f][x][kz][y0 + yl] = Aa[kz * kzstride + yl] (field fa), Aa[fstride + ...] (field fb)
     T2* Aa = A + a_index(g, fa, 0, x, y0);
-    const size_t kzstride = size_t(g.n1) * g.n2, fstride = size_t(g.h3) * kzstride;
+    const size_t kzstride = g.n2, fstride = size_t(g.n1) * g.h3 * g.n2;
     DivModStep ot(tid, nthr, ty);
 #pragma unroll 1
     for (int e = tid; e < nout; e += nthr, ot.next()) {
@@ -491,7 +493,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
   if (bad) *flag = 1;
 
   const int npairs = (M + 1) >> 1;
-  const size_t kzstride = size_t(g.n1) * g.n2, fstride = size_t(g.h3) * kzstride;
+  const size_t kzstride = g.n2, fstride = size_t(g.n1) * g.h3 * g.n2;
 #pragma unroll 1
   for (int pr0 = 0; pr0 < npairs; pr0 += PB) {
     const int nb = min(PB, npairs - pr0);
@@ -517,7 +519,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
           return T2{ta, tb};
         },
         LdsLines{});
-    // A[f][kz][x][y0 + yl] = Aa[kz * kzstride + yl] (field fa), Aa[fstride + ...] (field fb)
+    // A[f][x][kz][y0 + yl] = Aa[kz * kzstride + yl] (field fa), Aa[fstride + ...] (field fb)
     for (int q = 0; q < nb; ++q) {
       const int fa = 2 * (pr0 + q), fb = fa + 1;
       T2* Aa = A + a_index(g, fa, 0, x, y0);
@@ -542,7 +544,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
   }
 }
 
-// ---- pass 2 / 4: y FFT with rotation A[f][kz][x][y] <-> B[f][kz][ky][x] ----------------------
+// ---- pass 2 / 4: y FFT with rotation A[f][x][kz][y] <-> B[f][kz][ky][x] ----------------------
 // Block: TX consecutive x of one (f, kz) (blockIdx.x = x tile, .y = kz, .z = f).
 
 template <typename T, int EPT, int DIR>
@@ -562,6 +564,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
   // memory, the last inverse stage writes them there
   const bool f512 = n2 == 512 && (nthr & 63) == 0;
   const T2* twl = stage_twiddles(smem_raw, tw, g.n2, tid, nthr);
+  const size_t xs = size_t(g.h3) * g.n2;   // x stride of A
   if (DIR < 0 && f512) {
     // the staged twiddles are read from the second stage on, and the transform synchronises its
     // stages within each wave only
@@ -569,12 +572,12 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     const T2* sbase = src + a_index(g, f, kz, x0, 0);
     lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift>(
         line, tx, lstride, twl, tid, nthr,
-        [&](int xl, int, int y) { return (x0 + xl < g.n1) ? sbase[size_t(xl) * 512 + y] : T2{T(0), T(0)}; },
+        [&](int xl, int, int y) { return (x0 + xl < g.n1) ? sbase[size_t(xl) * xs + y] : T2{T(0), T(0)}; },
         LdsLines{});
   } else if (DIR < 0) {
     const T2* sbase = src + a_index(g, f, kz, x0, 0);
     gather_strided_dm<8>(
-        tid, nthr, tot, n2, [&](int e, int xl, int) { return (x0 + xl < g.n1) ? sbase[e] : T2{T(0), T(0)}; },
+        tid, nthr, tot, n2, [&](int, int xl, int y) { return (x0 + xl < g.n1) ? sbase[size_t(xl) * xs + y] : T2{T(0), T(0)}; },
         [&](int, int xl, int y, T2 v) { line[xl * lstride + lidx<>(y)] = v; });
   } else {
     // B[f][kz][ky][x0 + xl] = sbase[size_t(ky) * ystride + xl]
@@ -590,7 +593,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     T2* dbase = dst + a_index(g, f, kz, x0, 0);
     lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift, false>(line, tx, lstride, twl, tid, nthr, LdsLines{},
                                                        [&](int xl, int, int y, T2 v) {
-                                                         if (x0 + xl < g.n1) dbase[size_t(xl) * 512 + y] = v;
+                                                         if (x0 + xl < g.n1) dbase[size_t(xl) * xs + y] = v;
                                                        });
     return;
   }
@@ -611,7 +614,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     DivModStep it(tid, nthr, n2);
     for (int e = tid; e < tot; e += nthr, it.next()) {
       const int xl = it.q, y = it.r;
-      if (x0 + xl < g.n1) dbase[e] = line[xl * lstride + lidx<>(y)];
+      if (x0 + xl < g.n1) dbase[size_t(xl) * xs + y] = line[xl * lstride + lidx<>(y)];
     }
   }
 }
