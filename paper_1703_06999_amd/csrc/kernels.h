@@ -445,7 +445,7 @@ k_theta_zfwd(const double* __restrict__ nden, const double* __restrict__ sig,
 template <typename T, bool SIGMA_FROM_GRAD, int WPE, int PB>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
-                typename Cx<T>::type* __restrict__ A, Quad<T>* __restrict__ state, int* __restrict__ flag,
+                typename Cx<T>::type* __restrict__ A, Quad<T>* __restrict__ state, unsigned char* __restrict__ sb, int* __restrict__ flag,
                 const double* __restrict__ qmesh, const double* __restrict__ mm,
                 const typename Cx<T>::type* __restrict__ tw, Geometry g, int ty, int lstride) {
   using T2 = typename Cx<T>::type;
@@ -485,6 +485,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
       q0_state(in[r].n, sv, g.zab, S.q, M, b, t, an, as);
       // the point's spline state for the inverse z pass: (t, n dq0/dn, n dq0/dsigma, b)
       state[pbase + 64 * r] = Quad<T>{T(t), T(an), T(as), T(b < 0 ? 255 : b)};
+      sb[pbase + 64 * r] = (unsigned char)(b < 0 ? 255 : b);   // the interval alone, for the assembly
     }
     pb[r] = b < 0 ? 255 : b;
     pt[r] = T(t);
@@ -1288,6 +1289,7 @@ k_zinv_assemble(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __res
 template <typename T, int PB, int WPE, bool PREFETCH>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_zinv_assemble512(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __restrict__ state,
+                   const unsigned char* __restrict__ sb,
                    double* __restrict__ dedn, double* __restrict__ dedsig, const double* __restrict__ qmesh,
                    const double* __restrict__ mm, const typename Cx<T>::type* __restrict__ tw, Geometry g, int ty,
                    int lstride, const double* __restrict__ partials, int nparts, double escale,
@@ -1311,16 +1313,12 @@ k_zinv_assemble512(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __
   const int yl = __builtin_amdgcn_readfirstlane(tid >> 6), i = tid & 63, y = y0 + yl;
   const bool live = y < g.n2;
   const size_t pbase = (size_t(x) * g.n2 + y) * n3 + i;
-  // the spline interval of the thread's points, as the forward theta pass left it (the rest of
-  // the state, t, n dq0/dn and n dq0/dsigma, is read again after the transforms, which keeps it
-  // out of the registers the transforms need)
+  // the spline interval of the thread's points, as the forward theta pass left it in its byte
+  // array (the rest of the state, t, n dq0/dn and n dq0/dsigma, is read after the transforms,
+  // which keeps it out of the registers the transforms need)
   int pb[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    Quad<T> q{T(0), T(0), T(0), T(255)};
-    if (live) q = state[pbase + 64 * r];
-    pb[r] = int(q.w);
-  }
+  for (int r = 0; r < 8; ++r) pb[r] = live ? int(sb[pbase + 64 * r]) : 255;
   // Per point, with F_a the inverse transforms and m_c,a = p_a''(q_c):
   //   sum_a F_a p_a  = u F_b + t F_b+1 + c6 [(u^3-u) X0 + (t^3-t) X1]
   //   sum_a F_a p_a' = (F_b+1 - F_b)/h + (h/6) [-(3u^2-1) X0 + (3t^2-1) X1]

@@ -150,10 +150,11 @@ struct Launch {
 // carves one out of the static scratch array.  `timed`: record the per-stage HIP events (never on
 // the allocation-free path, where taking an event could allocate).
 struct Work {
-  void* A = nullptr;           // complex [f][kz][x][y] (z pass output), real fields of the div/grad passes
+  void* A = nullptr;           // complex [f][x][kz][y] (z pass output), real fields of the div/grad passes
   void* B = nullptr;           // complex [f][kz][ky][x] (y pass output)
   double* S = nullptr;         // dE/dsigma of the potential entry [N]
   void* state = nullptr;       // per-point spline state Quad<T> [N], theta pass -> assembly
+  unsigned char* sb = nullptr; // the spline interval alone [N] (512-point z lines), theta -> assembly
   double* G = nullptr;         // spectral gradient [3][N]
   double* partials = nullptr;  // per-column energy partials [N2 * H3]
   double* lda = nullptr;       // per-block sums of the LDA correlation pass [kLdaBlocks]
@@ -163,7 +164,7 @@ struct Work {
 
 // byte offsets of the buffers of Work in one block (each 256-byte aligned) and its size
 struct Layout {
-  size_t A, B, S, state, G, partials, lda, flag, total;
+  size_t A, B, S, state, sb, G, partials, lda, flag, total;
 };
 
 // bytes per grid point of the spline state passed from the theta pass to the assembly
@@ -184,6 +185,7 @@ Layout workspace_layout(int n1, int n2, int n3, vdwxc_precision p, int M) {
   L.B = o; o += al(cplx);
   L.S = o; o += al(N * sizeof(double));
   L.state = o; o += al(N * state_bytes(p));
+  L.sb = o; o += al(n3 == 512 ? N : 0);
   L.G = o; o += al(3 * N * sizeof(double));
   L.partials = o; o += al(size_t(n2) * (n3 / 2 + 1) * sizeof(double));
   L.lda = o; o += al(kLdaBlocks * sizeof(double));
@@ -199,6 +201,7 @@ Work carve(void* base, const Layout& L) {
   w.B = b + L.B;
   w.S = reinterpret_cast<double*>(b + L.S);
   w.state = b + L.state;
+  w.sb = b + L.sb;
   w.G = reinterpret_cast<double*>(b + L.G);
   w.partials = reinterpret_cast<double*>(b + L.partials);
   w.lda = reinterpret_cast<double*>(b + L.lda);
@@ -924,10 +927,10 @@ void enqueue_main(vdwxc_ctx* h, const Work& w, const double* n, const double* si
     const Launch& L5 = Prec<T>::z512(h);
     const dim3 g5((h->n2 + L5.tile - 1) / L5.tile, h->n1);
     if (sig_from_grad)
-      hipLaunchKernelGGL((k_theta_zfwd512<T, true, t512_wpe<T>(), t512_pb<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.flag,
+      hipLaunchKernelGGL((k_theta_zfwd512<T, true, t512_wpe<T>(), t512_pb<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.sb, w.flag,
                          tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride);
     else
-      hipLaunchKernelGGL((k_theta_zfwd512<T, false, t512_wpe<T>(), t512_pb<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.flag,
+      hipLaunchKernelGGL((k_theta_zfwd512<T, false, t512_wpe<T>(), t512_pb<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, n, sig, A, state, w.sb, w.flag,
                          tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride);
   } else if (sig_from_grad) {
     hipLaunchKernelGGL((k_theta_zfwd<T, kEPT, true>), zgrid, dim3(Lz.nthr), lds_theta, h->stream, n, sig, A, state,
@@ -957,7 +960,7 @@ void enqueue_main(vdwxc_ctx* h, const Work& w, const double* n, const double* si
     const Launch& L5 = Prec<T>::a512(h);
     const dim3 g5((h->n2 + L5.tile - 1) / L5.tile, h->n1);
     hipLaunchKernelGGL((k_zinv_assemble512<T, a512_pb<T>(), a512_wpe<T>(), a512_pf<T>()>), g5, dim3(L5.nthr), L5.lds, h->stream, A,
-                       state, dedn, dedsig, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride, w.partials,
+                       state, w.sb, dedn, dedsig, tb.d_q, tb.d_mm, Prec<T>::tw(h, 2), h->geo, L5.tile, L5.lstride, w.partials,
                        h->n2 * h->h3, h->omega / (2.0 * N * N), w.flag, energy);
   } else {
     hipLaunchKernelGGL((k_zinv_assemble<T, kEPTA, kEPTA, asm_pb<T>()>), agrid, dim3(La.nthr), lds_asm, h->stream, A, state,
