@@ -36,9 +36,11 @@ Readings where the paper is silent or garbled (each also listed in the design no
     F(r) = (1/N) sum_m F(m) exp(+2 pi i j.m/N), E = Omega/(2 N^2) sum_m sum_a Re[theta_a* F_a];
     this is eq. enlk with integrals replaced by the periodic-grid sums.
   * |G| of a frequency that sits on the Nyquist index of an even axis is ambiguous (+N/2 and
-    -N/2 alias); |G|^2 is taken as the mean over the two aliases, i.e. the Nyquist part and
-    the rest are added in quadrature.  This keeps phi(|G|) even in G, so F(k) stays Hermitian
-    and F(r) real; for orthogonal cells it is the plain |G|.
+    -N/2 alias).  G is split into the part from the non-Nyquist axes and the part from the
+    Nyquist axes (each taken at +N/2), and |G|^2 is the sum of their squared norms: the two are
+    added in quadrature, the Nyquist components among themselves are summed as vectors.  With
+    one Nyquist index this is the mean of |G|^2 over its two aliases.  It keeps phi(|G|) even in
+    G, so F(k) stays Hermitian and F(r) real; for orthogonal cells it is the plain |G|.
   * phi = 0 for |G| >= kmax of the table (callers reject such grids).
   * Potential entry: v = dE/dn - div(2 dE/dsigma grad n), the divergence (and, when no gradient
     is supplied, the gradient) taken spectrally with every Nyquist frequency zeroed.
