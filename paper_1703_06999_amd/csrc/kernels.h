@@ -731,6 +731,38 @@ __device__ __forceinline__ void buffer_load_quad(__amdgpu_buffer_rsrc_t r, int v
   __builtin_memcpy(&q.z, &hi, 16);
 }
 
+// Loads and stores of data each pass touches once (VDWXC_XNT: marked non-temporal, so that they do
+// not push the kernel table out of the caches)
+#ifndef VDWXC_XNT
+#define VDWXC_XNT 1
+#endif
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 stream_load(const double2* p) {
+  if constexpr (VDWXC_XNT) {
+    const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2*>(p));
+    return double2{v.x, v.y};
+  } else {
+    return *p;
+  }
+}
+__device__ __forceinline__ float2 stream_load(const float2* p) {
+  if constexpr (VDWXC_XNT) {
+    const nt_float2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float2*>(p));
+    return float2{v.x, v.y};
+  } else {
+    return *p;
+  }
+}
+__device__ __forceinline__ void stream_store(double2* p, double2 v) {
+  if constexpr (VDWXC_XNT) __builtin_nontemporal_store(nt_double2{v.x, v.y}, reinterpret_cast<nt_double2*>(p));
+  else *p = v;
+}
+__device__ __forceinline__ void stream_store(float2* p, float2 v) {
+  if constexpr (VDWXC_XNT) __builtin_nontemporal_store(nt_float2{v.x, v.y}, reinterpret_cast<nt_float2*>(p));
+  else *p = v;
+}
+
 // one half (T_j, D_j of one pair) of a table entry
 __device__ __forceinline__ void buffer_load_half(__amdgpu_buffer_rsrc_t r, int voff, int soff, float2& h) {
   const auto raw = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
@@ -794,7 +826,8 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
   const bool f512 = n1 == 512 && (nthr & 63) == 0 && M <= G;
   if (f512) {
     lds_fft512<(EPT + 7) / 8, -1, PS>(line, M, ls, twl, tid, nthr,
-                                      [&](int f, int, int x) { return cb[size_t(f) * fstride + x]; }, LdsLines{});
+                                      [&](int f, int, int x) { return stream_load(&cb[size_t(f) * fstride + x]); },
+                                      LdsLines{});
   } else {
     gather_strided_dm<16>(
         tid, nthr, M * n1, n1, [&](int, int f, int x) { return cb[size_t(f) * fstride + x]; },
@@ -959,7 +992,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     // 512-point columns: the last inverse stage stores straight to global memory (no LDS round
     // trip and barrier; it also frees registers: 18.4 -> 17.4 ms FP64, 11.1 -> 9.7 ms FP32 at 512^3)
     lds_fft512<(EPT + 7) / 8, +1, PS, false>(line, M, ls, twl, tid, nthr, LdsLines{},
-                                             [&](int f, int, int x, T2 v) { cb[size_t(f) * fstride + x] = v; });
+                                             [&](int f, int, int x, T2 v) { stream_store(&cb[size_t(f) * fstride + x], v); });
   } else {
     for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1, PS>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
     DivModStep it(tid, nthr, n1);
