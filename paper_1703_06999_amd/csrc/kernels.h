@@ -47,6 +47,82 @@ struct alignas(4 * sizeof(T)) Quad {
   T x, y, z, w;
 };
 
+// Non-temporal loads and stores, for data a pass touches once: they do not displace what the
+// caches should keep (the kernel table of the contraction).  ld<NT> / st<NT> pick them or plain
+// accesses at compile time.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+typedef double nt_double4 __attribute__((ext_vector_type(4)));
+typedef float nt_float4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 nt_load(const double2* p) {
+  const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2*>(p));
+  return double2{v.x, v.y};
+}
+__device__ __forceinline__ float2 nt_load(const float2* p) {
+  const nt_float2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float2*>(p));
+  return float2{v.x, v.y};
+}
+__device__ __forceinline__ Quad<double> nt_load(const Quad<double>* p) {
+  const nt_double4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double4*>(p));
+  return Quad<double>{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ Quad<float> nt_load(const Quad<float>* p) {
+  const nt_float4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float4*>(p));
+  return Quad<float>{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ void nt_store(double2* p, double2 v) {
+  __builtin_nontemporal_store(nt_double2{v.x, v.y}, reinterpret_cast<nt_double2*>(p));
+}
+__device__ __forceinline__ void nt_store(float2* p, float2 v) {
+  __builtin_nontemporal_store(nt_float2{v.x, v.y}, reinterpret_cast<nt_float2*>(p));
+}
+__device__ __forceinline__ void nt_store(Quad<double>* p, Quad<double> v) {
+  __builtin_nontemporal_store(nt_double4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_double4*>(p));
+}
+__device__ __forceinline__ void nt_store(Quad<float>* p, Quad<float> v) {
+  __builtin_nontemporal_store(nt_float4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_float4*>(p));
+}
+__device__ __forceinline__ void nt_store(double* p, double v) { __builtin_nontemporal_store(v, p); }
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const V* p) {
+  if constexpr (NT) return nt_load(p);
+  else return *p;
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void st(V* p, V v) {
+  if constexpr (NT) nt_store(p, v);
+  else *p = v;
+}
+// the contraction pass's column accesses
+#ifndef VDWXC_XNT
+#define VDWXC_XNT 1
+#endif
+constexpr bool kNtX = VDWXC_XNT;
+// the streaming accesses of the other passes, per site and precision (bit masks of NtSite)
+enum NtSite {
+  kNtThetaOut = 1,    // theta pass: half spectra and spline state
+  kNtYfLoad = 2,      // forward y pass: A lines
+  kNtYfStore = 4,     // forward y pass: B rows
+  kNtYiLoad = 8,      // inverse y pass: B rows
+  kNtYiStore = 16,    // inverse y pass: A lines
+  kNtAsmA = 32,       // assembly: half spectra
+  kNtAsmState = 64,   // assembly: spline state
+  kNtAsmOut = 128     // assembly: dE/dn, dE/dsigma
+};
+// (at 512^3: FP64 theta, y and contraction 52.2 -> 50.7 ms/step with sites 1-16; FP32 30.4 -> 30.0
+// with sites 1-4.  Non-temporal reads of the assembly's half spectra, and of the FP32 inverse y
+// pass's rows, were slower: 7.25 -> 7.45 ms and 5.2 -> 6.6 ms, 4.2 -> 4.6 ms.)
+#ifndef VDWXC_NT64
+#define VDWXC_NT64 (kNtThetaOut | kNtYfLoad | kNtYfStore | kNtYiLoad | kNtYiStore)
+#endif
+#ifndef VDWXC_NT32
+#define VDWXC_NT32 (kNtThetaOut | kNtYfLoad | kNtYfStore)
+#endif
+template <typename T, int SITE>
+constexpr bool nt_site() {
+  return (((sizeof(T) == 8) ? VDWXC_NT64 : VDWXC_NT32) & SITE) != 0;
+}
+
 // ---- q0, saturation and the helper splines (per grid point, FP64) ----------------------------
 
 // PW92 LDA correlation energy per electron eps_c(r_s) of the paper's appendix (spin-paired) and
@@ -484,7 +560,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
       double an, as;
       q0_state(in[r].n, sv, g.zab, S.q, M, b, t, an, as);
       // the point's spline state for the inverse z pass: (t, n dq0/dn, n dq0/dsigma, b)
-      state[pbase + 64 * r] = Quad<T>{T(t), T(an), T(as), T(b < 0 ? 255 : b)};
+      st<nt_site<T, kNtThetaOut>()>(&state[pbase + 64 * r], Quad<T>{T(t), T(an), T(as), T(b < 0 ? 255 : b)});
       sb[pbase + 64 * r] = (unsigned char)(b < 0 ? 255 : b);   // the interval alone, for the assembly
     }
     pb[r] = b < 0 ? 255 : b;
@@ -536,8 +612,8 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
           T2 xa, xb;
           split_pair(zk, zn, xa, xb);
           T2* dst = Aa + size_t(kz) * kzstride + ol;
-          dst[0] = xa;
-          if (fb < M) dst[fstride] = xb;
+          st<nt_site<T, kNtThetaOut>()>(dst, xa);
+          if (fb < M) st<nt_site<T, kNtThetaOut>()>(dst + fstride, xb);
         }
       }
     }
@@ -573,7 +649,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     const T2* sbase = src + a_index(g, f, kz, x0, 0);
     lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift>(
         line, tx, lstride, twl, tid, nthr,
-        [&](int xl, int, int y) { return (x0 + xl < g.n1) ? sbase[size_t(xl) * xs + y] : T2{T(0), T(0)}; },
+        [&](int xl, int, int y) { return (x0 + xl < g.n1) ? ld<nt_site<T, kNtYfLoad>()>(&sbase[size_t(xl) * xs + y]) : T2{T(0), T(0)}; },
         LdsLines{});
   } else if (DIR < 0) {
     const T2* sbase = src + a_index(g, f, kz, x0, 0);
@@ -586,7 +662,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     const int ystride = g.n1;
     gather_strided_dm<8>(
         tid, nthr, tot, tx,
-        [&](int, int ky, int xl) { return (x0 + xl < g.n1) ? sbase[size_t(ky) * ystride + xl] : T2{T(0), T(0)}; },
+        [&](int, int ky, int xl) { return (x0 + xl < g.n1) ? ld<nt_site<T, kNtYiLoad>()>(&sbase[size_t(ky) * ystride + xl]) : T2{T(0), T(0)}; },
         [&](int, int ky, int xl, T2 v) { line[xl * lstride + lidx<>(ky)] = v; });
   }
   if (DIR > 0 && f512) {
@@ -594,7 +670,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     T2* dbase = dst + a_index(g, f, kz, x0, 0);
     lds_fft512<(EPT + 7) / 8, DIR, kLdsPadShift, false>(line, tx, lstride, twl, tid, nthr, LdsLines{},
                                                        [&](int xl, int, int y, T2 v) {
-                                                         if (x0 + xl < g.n1) dbase[size_t(xl) * xs + y] = v;
+                                                         if (x0 + xl < g.n1) st<nt_site<T, kNtYiStore>()>(&dbase[size_t(xl) * xs + y], v);
                                                        });
     return;
   }
@@ -608,7 +684,7 @@ k_ypass(const typename Cx<T>::type* __restrict__ src, typename Cx<T>::type* __re
     DivModStep it(tid, nthr, tx);
     for (int e = tid; e < tot; e += nthr, it.next()) {
       const int xl = it.r, ky = it.q;
-      if (x0 + xl < g.n1) dbase[size_t(ky) * ystride + xl] = line[xl * lstride + lidx<>(ky)];
+      if (x0 + xl < g.n1) st<nt_site<T, kNtYfStore>()>(&dbase[size_t(ky) * ystride + xl], line[xl * lstride + lidx<>(ky)]);
     }
   } else {
     T2* dbase = dst + a_index(g, f, kz, x0, 0);
@@ -731,38 +807,6 @@ __device__ __forceinline__ void buffer_load_quad(__amdgpu_buffer_rsrc_t r, int v
   __builtin_memcpy(&q.z, &hi, 16);
 }
 
-// Loads and stores of data each pass touches once (VDWXC_XNT: marked non-temporal, so that they do
-// not push the kernel table out of the caches)
-#ifndef VDWXC_XNT
-#define VDWXC_XNT 1
-#endif
-typedef double nt_double2 __attribute__((ext_vector_type(2)));
-typedef float nt_float2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ double2 stream_load(const double2* p) {
-  if constexpr (VDWXC_XNT) {
-    const nt_double2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_double2*>(p));
-    return double2{v.x, v.y};
-  } else {
-    return *p;
-  }
-}
-__device__ __forceinline__ float2 stream_load(const float2* p) {
-  if constexpr (VDWXC_XNT) {
-    const nt_float2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_float2*>(p));
-    return float2{v.x, v.y};
-  } else {
-    return *p;
-  }
-}
-__device__ __forceinline__ void stream_store(double2* p, double2 v) {
-  if constexpr (VDWXC_XNT) __builtin_nontemporal_store(nt_double2{v.x, v.y}, reinterpret_cast<nt_double2*>(p));
-  else *p = v;
-}
-__device__ __forceinline__ void stream_store(float2* p, float2 v) {
-  if constexpr (VDWXC_XNT) __builtin_nontemporal_store(nt_float2{v.x, v.y}, reinterpret_cast<nt_float2*>(p));
-  else *p = v;
-}
-
 // one half (T_j, D_j of one pair) of a table entry
 __device__ __forceinline__ void buffer_load_half(__amdgpu_buffer_rsrc_t r, int voff, int soff, float2& h) {
   const auto raw = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
@@ -826,7 +870,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
   const bool f512 = n1 == 512 && (nthr & 63) == 0 && M <= G;
   if (f512) {
     lds_fft512<(EPT + 7) / 8, -1, PS>(line, M, ls, twl, tid, nthr,
-                                      [&](int f, int, int x) { return stream_load(&cb[size_t(f) * fstride + x]); },
+                                      [&](int f, int, int x) { return ld<kNtX>(&cb[size_t(f) * fstride + x]); },
                                       LdsLines{});
   } else {
     gather_strided_dm<16>(
@@ -992,7 +1036,7 @@ k_xcontract(typename Cx<T>::type* __restrict__ B, const Quad<T>* __restrict__ ta
     // 512-point columns: the last inverse stage stores straight to global memory (no LDS round
     // trip and barrier; it also frees registers: 18.4 -> 17.4 ms FP64, 11.1 -> 9.7 ms FP32 at 512^3)
     lds_fft512<(EPT + 7) / 8, +1, PS, false>(line, M, ls, twl, tid, nthr, LdsLines{},
-                                             [&](int f, int, int x, T2 v) { stream_store(&cb[size_t(f) * fstride + x], v); });
+                                             [&](int f, int, int x, T2 v) { st<kNtX>(&cb[size_t(f) * fstride + x], v); });
   } else {
     for (int l0 = 0; l0 < M; l0 += G) lds_fft<EPT, +1, PS>(line + l0 * ls, xp, min(G, M - l0), ls, twl, tid, nthr);
     DivModStep it(tid, nthr, n1);
@@ -1045,8 +1089,8 @@ struct PairPrefetch {
       if (e < tot) {
         const int yl = it.r, kz = it.q, y = y0 + yl;
         if (y < g.n2) {
-          a[c] = A[a_index(g, fa, kz, x, y)];
-          if (fb >= 0) b[c] = A[a_index(g, fb, kz, x, y)];
+          a[c] = ld<nt_site<T, kNtAsmA>()>(&A[a_index(g, fa, kz, x, y)]);
+          if (fb >= 0) b[c] = ld<nt_site<T, kNtAsmA>()>(&A[a_index(g, fb, kz, x, y)]);
         }
       }
     }
@@ -1408,15 +1452,15 @@ k_zinv_assemble512(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __
   }
   if (live) {
     const double invN = 1.0 / double(N);
-    Quad<T> st[8];
+    Quad<T> stv[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) st[r] = state[pbase + 64 * r];
+    for (int r = 0; r < 8; ++r) stv[r] = ld<nt_site<T, kNtAsmState>()>(&state[pbase + 64 * r]);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       double vn = 0.0, vs = 0.0;
       const int b = pb[r];
       if (b != 255) {
-        const double t = st[r].x, an = st[r].y, as = st[r].z;
+        const double t = stv[r].x, an = stv[r].y, as = stv[r].z;
         const double hh = S.h[b], c6 = S.c6[b], u = 1.0 - t;
         const double fb0 = Fb[r], fb1 = Fb1[r];
         const double P = u * fb0 + t * fb1 + c6 * ((u * u * u - u) * X0[r] + (t * t * t - t) * X1[r]);
@@ -1424,8 +1468,8 @@ k_zinv_assemble512(const typename Cx<T>::type* __restrict__ A, const Quad<T>* __
         vn = P + an * D;
         vs = as * D;
       }
-      dedn[pbase + 64 * r] = vn * invN;
-      dedsig[pbase + 64 * r] = vs * invN;
+      st<nt_site<T, kNtAsmOut>()>(&dedn[pbase + 64 * r], vn * invN);
+      st<nt_site<T, kNtAsmOut>()>(&dedsig[pbase + 64 * r], vs * invN);
     }
   }
 }
