@@ -82,7 +82,9 @@ __device__ __forceinline__ void nt_store(Quad<double>* p, Quad<double> v) {
 __device__ __forceinline__ void nt_store(Quad<float>* p, Quad<float> v) {
   __builtin_nontemporal_store(nt_float4{v.x, v.y, v.z, v.w}, reinterpret_cast<nt_float4*>(p));
 }
+__device__ __forceinline__ double nt_load(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void nt_store(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(float* p, float v) { __builtin_nontemporal_store(v, p); }
 template <bool NT, typename V>
 __device__ __forceinline__ V ld(const V* p) {
   if constexpr (NT) return nt_load(p);
@@ -107,16 +109,19 @@ enum NtSite {
   kNtYiStore = 16,    // inverse y pass: A lines
   kNtAsmA = 32,       // assembly: half spectra
   kNtAsmState = 64,   // assembly: spline state
-  kNtAsmOut = 128     // assembly: dE/dn, dE/dsigma
+  kNtAsmOut = 128,    // assembly: dE/dn, dE/dsigma
+  kNtDivZLoad = 256,  // z divergence pass: dE/dsigma and the gradient
+  kNtDivZStore = 512  // z divergence pass: its three outputs
 };
 // (at 512^3: FP64 theta, y and contraction 52.2 -> 50.7 ms/step with sites 1-16; FP32 30.4 -> 30.0
-// with sites 1-4.  Non-temporal reads of the assembly's half spectra, and of the FP32 inverse y
-// pass's rows, were slower: 7.25 -> 7.45 ms and 5.2 -> 6.6 ms, 4.2 -> 4.6 ms.)
+// with sites 1-4, z divergence 1.09 -> 0.99 ms FP32 with its sites (FP64: 1.89 -> 1.96, so not
+// there).  Non-temporal reads of the assembly's half spectra, and of the FP32 inverse y pass's rows,
+// were slower: 7.25 -> 7.45 ms and 5.2 -> 6.6 ms, 4.2 -> 4.6 ms.)
 #ifndef VDWXC_NT64
 #define VDWXC_NT64 (kNtThetaOut | kNtYfLoad | kNtYfStore | kNtYiLoad | kNtYiStore)
 #endif
 #ifndef VDWXC_NT32
-#define VDWXC_NT32 (kNtThetaOut | kNtYfLoad | kNtYfStore)
+#define VDWXC_NT32 (kNtThetaOut | kNtYfLoad | kNtYfStore | kNtDivZLoad | kNtDivZStore)
 #endif
 template <typename T, int SITE>
 constexpr bool nt_site() {
@@ -1579,10 +1584,11 @@ k_div_z(const double* __restrict__ S, const double* __restrict__ grad, T* __rest
         In r{0.0, 0.0, 0.0, 0.0};
         if (y < g.n2) {
           const size_t idx = (size_t(x) * g.n2 + y) * n3 + z;
-          r.s = S[idx];
-          r.g0 = grad[idx];
-          r.g1 = grad[N + idx];
-          r.g2 = grad[2 * N + idx];
+          constexpr bool nt = nt_site<T, kNtDivZLoad>();
+          r.s = ld<nt>(&S[idx]);
+          r.g0 = ld<nt>(&grad[idx]);
+          r.g1 = ld<nt>(&grad[N + idx]);
+          r.g2 = ld<nt>(&grad[2 * N + idx]);
         }
         return r;
       },
@@ -1606,9 +1612,10 @@ k_div_z(const double* __restrict__ S, const double* __restrict__ grad, T* __rest
       const T2 p = pl[yl * lstride + lidx<>(z)], c = csum[yl];
       const T2 d = dl[(yl >> 1) * lstride + lidx<>(z)];
       const T sg = (z & 1) ? T(-1) : T(1);
-      out[idx] = (yl & 1) ? d.y : d.x;
-      out[N + idx] = p.x - sg * c.x;
-      out[2 * N + idx] = p.y - sg * c.y;
+      constexpr bool nt = nt_site<T, kNtDivZStore>();
+      st<nt>(&out[idx], (yl & 1) ? d.y : d.x);
+      st<nt>(&out[N + idx], p.x - sg * c.x);
+      st<nt>(&out[2 * N + idx], p.y - sg * c.y);
     }
   }
 }

@@ -70,14 +70,16 @@ constexpr int t512_pb() { return sizeof(T) == 8 ? VDWXC_T512_PB64 : VDWXC_T512_P
 template <typename T>
 constexpr int a512_pb() { return sizeof(T) == 8 ? VDWXC_A512_PB64 : 1; }
 #ifndef VDWXC_A512_WPE32
-#define VDWXC_A512_WPE32 4
+#define VDWXC_A512_WPE32 2
 #endif
-// Measured at 512^3: FP64 14.3 -> 12.6 ms (8-line blocks, no prefetch; prefetching the next pair
-// measured 12.9); in FP32 the register-state version loses to the general kernel (7.9 ms against
-// 11.7 with 8-line blocks at four waves per SIMD, 9.5 with 4-line blocks at three), so FP32 keeps
-// k_zinv_assemble.
+// Measured at 512^3 when it was introduced: FP64 14.3 -> 12.6 ms (8-line blocks, no prefetch;
+// prefetching the next pair measured 12.9), while in FP32 the register-state version lost to the
+// general kernel (7.9 ms against 11.7 with 8-line blocks at four waves per SIMD, 9.5 with 4-line
+// blocks at three).  With the interval byte array, the state read after the transforms and the
+// wave-synchronised stages it wins in FP32 too at two waves per SIMD with the next pair prefetched:
+// 5.24 -> 5.01 ms (four waves: 6.0 ms with spills; three: 8.0 ms).
 #ifndef VDWXC_A512_FP32
-#define VDWXC_A512_FP32 0
+#define VDWXC_A512_FP32 1
 #endif
 template <typename T>
 constexpr bool a512_used() { return sizeof(T) == 8 ? true : VDWXC_A512_FP32; }
@@ -87,7 +89,7 @@ constexpr int a512_wpe() { return sizeof(T) == 8 ? VDWXC_A512_WPE64 : VDWXC_A512
 #define VDWXC_A512_PF64 1
 #endif
 #ifndef VDWXC_A512_PF32
-#define VDWXC_A512_PF32 0
+#define VDWXC_A512_PF32 1
 #endif
 template <typename T>
 constexpr bool a512_pf() { return sizeof(T) == 8 ? VDWXC_A512_PF64 : VDWXC_A512_PF32; }
