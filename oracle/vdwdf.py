@@ -19,7 +19,8 @@ Steps (Sec. 3, Table 1, and the enumerated procedure of Sec. 3):
   5. F_a(r) by inverse FFT                                      (Sec. 3, step 4)
   6. dE/dn, dE/dsigma                                           (Sec. 2, eqs. dedn and dedsigma)
 and, beside the nonlocal path, the semilocal LDA correlation E_c^LDA, v_c^LDA of eq. 1's split
-(PW92, appendix).
+(PW92, appendix), and the spin-polarised variant that Sec. 7 announces (q0 from the two spin
+densities; steps 2-5 unchanged).
 
 Readings where the paper is silent or garbled (each also listed in the design notes):
   * r_s = (3/(4 pi n))^{1/3}, the Wigner-Seitz radius (the appendix prints r_s^3 = 4 pi n/3,
@@ -44,6 +45,16 @@ Readings where the paper is silent or garbled (each also listed in the design no
   * phi = 0 for |G| >= kmax of the table (callers reject such grids).
   * Potential entry: v = dE/dn - div(2 dE/dsigma grad n), the divergence (and, when no gradient
     is supplied, the gradient) taken spectrally with every Nyquist frequency zeroed.
+  * Spin polarisation (Sec. 7 announces it; the paper prints no formula, so this part is pinned
+    only through its reductions, limits and finite differences): theta_a = n p_a(q0) with the
+    total density n = n_up + n_dn, and q0 = -(4 pi/3) eps_xc^0 with the gradient-corrected LDA
+    exchange of the appendix spin-scaled, E_x[n_up, n_dn] = (E_x[2 n_up] + E_x[2 n_dn])/2, and the
+    spin-resolved PW92 correlation eps_c(r_s, zeta):
+        q0 = sum_s (n_s/n) k_s [1 - (Z_ab/9) sigma_ss / (4 k_s^2 n_s^2)] - (4 pi/3) eps_c(r_s, zeta)
+    with k_s = (6 pi^2 n_s)^{1/3} = k_F(2 n_s); at n_up = n_dn, sigma_uu = sigma_dd = sigma/4 it is
+    the spin-paired q0.  A spin density below 1e-30 (negative ones included) is taken as zero.
+    eps_c(r_s, 1) and the spin stiffness alpha_c(r_s) use Perdew and Wang's published fits (the
+    paper prints only the zeta = 0 one).  Saturation, clamp and vacuum as spin-paired.
 """
 from __future__ import annotations
 
@@ -62,6 +73,11 @@ PW92_A = 0.031091
 PW92_ALPHA1 = 0.2137
 PW92_BETA = (7.5957, 3.5876, 1.6382, 0.49294)
 ZAB = {"DF1": -0.8491, "DF2": -1.887}
+# spin-resolved PW92 fits (Perdew and Wang 1992): (A, alpha1, beta1..4) of eps_c(r_s, 1) and of
+# -alpha_c(r_s), and f''(0) of the spin interpolation f(zeta); the zeta = 0 set is the appendix's
+PW92_FERRO = (0.015545, 0.20548, (14.1189, 6.1977, 3.3662, 0.62517))
+PW92_MINUS_ALPHA = (0.016887, 0.11125, (10.357, 3.6231, 0.88026, 0.49671))
+PW92_FZZ0 = 1.709921
 SATURATION_A = 5.0
 SATURATION_TERMS = 12
 VACUUM_DENSITY = 1e-30
@@ -133,6 +149,51 @@ def lda_correlation(n, cell):
     return E, v
 
 
+def pw92_G(rs, A, alpha1, beta):
+    """The PW92 form G(r_s) = -2A (1 + alpha1 r_s) log[1 + 1/(2A sum_{i=1..4} beta_i r_s^{i/2})]
+    for one parameter set, and dG/dr_s."""
+    rs = np.asarray(rs, dtype=np.float64)
+    b1, b2, b3, b4 = beta
+    sq = np.sqrt(rs)
+    Q = 2.0 * A * (b1 * sq + b2 * rs + b3 * rs * sq + b4 * rs * rs)
+    dQ = 2.0 * A * (0.5 * b1 / sq + b2 + 1.5 * b3 * sq + 2.0 * b4 * rs)
+    L = np.log1p(1.0 / Q)
+    G = -2.0 * A * (1.0 + alpha1 * rs) * L
+    dG = -2.0 * A * alpha1 * L + 2.0 * A * (1.0 + alpha1 * rs) * dQ / (Q * Q + Q)
+    return G, dG
+
+
+def spin_interpolation(zeta):
+    """f(zeta) = [(1+zeta)^{4/3} + (1-zeta)^{4/3} - 2] / (2^{4/3} - 2) and f'(zeta)."""
+    z = np.asarray(zeta, dtype=np.float64)
+    den = 2.0 ** (4.0 / 3.0) - 2.0
+    up, dn = np.cbrt(1.0 + z), np.cbrt(1.0 - z)
+    f = ((1.0 + z) * up + (1.0 - z) * dn - 2.0) / den
+    df = (4.0 / 3.0) * (up - dn) / den
+    return f, df
+
+
+def pw92_spin_correlation(rs, zeta):
+    """Spin-polarised PW92 correlation energy per particle
+        eps_c(r_s, zeta) = eps_c(r_s, 0) + alpha_c(r_s) f(zeta)/f''(0) (1 - zeta^4)
+                           + [eps_c(r_s, 1) - eps_c(r_s, 0)] f(zeta) zeta^4
+    (eps_c(r_s, 0) the appendix's form; eps_c(r_s, 1) and -alpha_c fitted by the same form) and its
+    partials in r_s and zeta.  Returns (eps, d eps/d r_s, d eps/d zeta)."""
+    rs = np.asarray(rs, dtype=np.float64)
+    z = np.asarray(zeta, dtype=np.float64)
+    e0, de0 = pw92_correlation(rs)
+    e1, de1 = pw92_G(rs, *PW92_FERRO)
+    ma, dma = pw92_G(rs, *PW92_MINUS_ALPHA)
+    ac, dac = -ma, -dma
+    f, df = spin_interpolation(z)
+    z4 = z ** 4
+    eps = e0 + ac * f / PW92_FZZ0 * (1.0 - z4) + (e1 - e0) * f * z4
+    deps_drs = de0 + dac * f / PW92_FZZ0 * (1.0 - z4) + (de1 - de0) * f * z4
+    deps_dz = (ac / PW92_FZZ0 * (df * (1.0 - z4) - 4.0 * z ** 3 * f)
+               + (e1 - e0) * (df * z4 + 4.0 * z ** 3 * f))
+    return eps, deps_drs, deps_dz
+
+
 def saturation(x, a=SATURATION_A):
     """h_a(x) = a [1 - exp(-sum_{m=1}^{12} (x/a)^m / m)] and its derivative h_a'(x)  (appendix)."""
     x = np.asarray(x, dtype=np.float64)
@@ -182,6 +243,61 @@ def q0_and_derivatives(n, sigma, qmesh, zab):
     dq_dn = np.where(below | vac, 0.0, dq_dn)
     dq_ds = np.where(below | vac, 0.0, dq_ds)
     return q0, dq_dn, dq_ds, vac
+
+
+def q0_spin_unsaturated(n_up, n_dn, s_uu, s_dd, zab):
+    """Unsaturated spin-polarised q0 (the reading in the header) for n = n_up + n_dn >= 1e-30, with
+    its partials in n_up, n_dn, sigma_uu, sigma_dd.  Spin densities below 1e-30 count as zero (that
+    channel drops out; n still moves with it, d n / d n_s = 1).  Returns (x, dx/dn_up, dx/dn_dn,
+    dx/dsigma_uu, dx/dsigma_dd)."""
+    nu = np.asarray(n_up, dtype=np.float64)
+    nd = np.asarray(n_dn, dtype=np.float64)
+    su = np.asarray(s_uu, dtype=np.float64)
+    sd = np.asarray(s_dd, dtype=np.float64)
+    live_u, live_d = nu >= VACUUM_DENSITY, nd >= VACUUM_DENSITY
+    nu = np.where(live_u, nu, 0.0)
+    nd = np.where(live_d, nd, 0.0)
+    n = nu + nd
+    # exchange: sum_s (n_s/n) k_s [1 - (Z_ab/9) s_s^2],  s_s^2 = sigma_ss / (4 k_s^2 n_s^2)
+    X = np.zeros_like(n)
+    dX = []       # d/dn_s of the channel's own term (n held fixed), d/dsigma_ss
+    for ns, ss, live in ((nu, su, live_u), (nd, sd, live_d)):
+        nsafe = np.where(live, ns, 1.0)
+        ks = np.cbrt(6.0 * math.pi ** 2 * nsafe)
+        term = ns / n * ks - (zab / 36.0) * ss / (n * nsafe * ks)
+        dterm_dns = (4.0 / 3.0) * ks / n + (zab / 27.0) * ss / (n * nsafe ** 2 * ks)
+        dterm_dss = -(zab / 36.0) / (n * nsafe * ks)
+        X = X + np.where(live, term, 0.0)
+        dX.append((np.where(live, dterm_dns, 0.0), np.where(live, dterm_dss, 0.0)))
+    # correlation: eps_c(r_s, zeta), r_s = (3/(4 pi n))^{1/3}, zeta = (n_up - n_dn)/n
+    rs = np.cbrt(3.0 / (4.0 * math.pi * n))
+    zeta = (nu - nd) / n
+    ec, dec_drs, dec_dz = pw92_spin_correlation(rs, zeta)
+    x = X - (4.0 * math.pi / 3.0) * ec
+    drs_dn = -rs / (3.0 * n)
+    dx_dnu = dX[0][0] - X / n - (4.0 * math.pi / 3.0) * (dec_drs * drs_dn + dec_dz * (1.0 - zeta) / n)
+    dx_dnd = dX[1][0] - X / n - (4.0 * math.pi / 3.0) * (dec_drs * drs_dn - dec_dz * (1.0 + zeta) / n)
+    return x, dx_dnu, dx_dnd, dX[0][1], dX[1][1]
+
+
+def q0_spin_and_derivatives(n_up, n_dn, s_uu, s_dd, qmesh, zab):
+    """Saturated spin-polarised q0 with its four partials and the vacuum mask (n_up + n_dn below
+    1e-30 after the per-channel cut), saturation and clamp as in q0_and_derivatives."""
+    nu = np.asarray(n_up, dtype=np.float64)
+    nd = np.asarray(n_dn, dtype=np.float64)
+    n = np.where(nu >= VACUUM_DENSITY, nu, 0.0) + np.where(nd >= VACUUM_DENSITY, nd, 0.0)
+    vac = ~(n >= VACUUM_DENSITY)
+    # vacuum points: any live stand-in (masked below)
+    nu_s = np.where(vac, 1.0, nu)
+    nd_s = np.where(vac, 1.0, nd)
+    zero = lambda a: np.where(vac, 0.0, np.asarray(a, dtype=np.float64))
+    x, *dx = q0_spin_unsaturated(nu_s, nd_s, zero(s_uu), zero(s_dd), zab)
+    q0, hp = saturation(x)
+    dq = [np.where(hp == 0.0, 0.0, hp * np.where(hp == 0.0, 0.0, d)) for d in dx]
+    below = q0 < qmesh[0]
+    q0 = np.where(below, qmesh[0], q0)
+    dq = [np.where(below | vac, 0.0, d) for d in dq]
+    return q0, dq, vac, np.where(vac, 0.0, n)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -264,6 +380,34 @@ def theta_and_derivatives(n, sigma, qmesh, zab):
     _map_chunks(points, nf.size, 1 << 16)
     shape = (M,) + n.shape
     return theta.reshape(shape), dtheta_dn.reshape(shape), dtheta_ds.reshape(shape)
+
+
+def theta_and_derivatives_spin(n_up, n_dn, s_uu, s_dd, qmesh, zab):
+    """Spin-polarised theta_a = n p_a(q0) (n = n_up + n_dn) and the factors of the four partial
+    derivatives: dtheta_a/dn_s = p_a + n p_a' dq0/dn_s, dtheta_a/dsigma_ss = n p_a' dq0/dsigma_ss.
+    Returns (theta, [dtheta/dn_up, dtheta/dn_dn, dtheta/dsigma_uu, dtheta/dsigma_dd])."""
+    nu = np.asarray(n_up, dtype=np.float64)
+    shape = nu.shape
+    args = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), shape)).reshape(-1)
+            for a in (n_up, n_dn, s_uu, s_dd)]
+    coeffs = spline_coefficients(qmesh)
+    M = len(qmesh)
+    size = args[0].size
+    theta = np.empty((M, size))
+    dtheta = [np.empty((M, size)) for _ in range(4)]
+
+    def points(s, e):
+        q0, dq, vac, n = q0_spin_and_derivatives(*(a[s:e] for a in args), qmesh, zab)
+        p, dp = spline_values(qmesh, coeffs, q0)
+        theta[:, s:e] = n * p
+        dtheta[0][:, s:e] = np.where(vac, 0.0, p + n * dp * dq[0])
+        dtheta[1][:, s:e] = np.where(vac, 0.0, p + n * dp * dq[1])
+        dtheta[2][:, s:e] = n * dp * dq[2]
+        dtheta[3][:, s:e] = n * dp * dq[3]
+
+    _map_chunks(points, size, 1 << 16)
+    out = (M,) + shape
+    return theta.reshape(out), [d.reshape(out) for d in dtheta]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -399,6 +543,20 @@ class _Steps:
             self.t = now
 
 
+def _nonlocal_fields(theta, knorm, table, kmax, omega, steps):
+    """Steps 2-4 of Sec. 3 on the theta fields: forward FFT, contraction with the energy sum,
+    inverse FFT.  Returns (E, F(r), theta(k), F(k))."""
+    N = theta[0].size
+    theta_k = forward_fft(theta)                                                    # step 2
+    steps.done("forward FFT")
+    F_k, esum = kspace_contraction(theta_k, knorm, table, kmax)                    # step 3
+    steps.done("contraction")
+    E = omega / (2.0 * N * N) * esum
+    F = inverse_fft(F_k)                                                            # step 4
+    steps.done("inverse FFT")
+    return E, F, theta_k, F_k
+
+
 def energy_and_partials(n, sigma, cell, kernel, flavour="DF1", return_intermediates=False, progress=None):
     """E_c^nl and the partial derivatives dE/dn, dE/dsigma as fields (Sec. 2, eqs. dedn and
     dedsigma; Sec. 3 procedure).  Returns (E, dedn, dedsigma[, dict]).  ``progress``, if given, is
@@ -409,7 +567,6 @@ def energy_and_partials(n, sigma, cell, kernel, flavour="DF1", return_intermedia
     grid = n.shape
     check_inputs(grid, cell, n, sigma)
     table, kmax, qmesh = _as_table(kernel)
-    N = n.size
     omega = float(np.linalg.det(np.asarray(cell, dtype=np.float64)))
     knorm = gvector_norms(grid, cell)
     if np.max(knorm) >= kmax:
@@ -417,13 +574,7 @@ def energy_and_partials(n, sigma, cell, kernel, flavour="DF1", return_intermedia
 
     theta, dth_dn, dth_ds = theta_and_derivatives(n, sigma, qmesh, ZAB[flavour])   # step 1
     steps.done("q0 + theta")
-    theta_k = forward_fft(theta)                                                    # step 2
-    steps.done("forward FFT")
-    F_k, esum = kspace_contraction(theta_k, knorm, table, kmax)                    # step 3
-    steps.done("contraction")
-    E = omega / (2.0 * N * N) * esum
-    F = inverse_fft(F_k)                                                            # step 4
-    steps.done("inverse FFT")
+    E, F, theta_k, F_k = _nonlocal_fields(theta, knorm, table, kmax, omega, steps)  # steps 2-4
     dedn = np.sum(F * dth_dn, axis=0)                                               # step 5
     dedsigma = np.sum(F * dth_ds, axis=0)
     steps.done("derivatives")
@@ -431,6 +582,28 @@ def energy_and_partials(n, sigma, cell, kernel, flavour="DF1", return_intermedia
         return E, dedn, dedsigma, dict(theta=theta, theta_k=theta_k, F_k=F_k, F=F,
                                        dtheta_dn=dth_dn, dtheta_dsigma=dth_ds, knorm=knorm)
     return E, dedn, dedsigma
+
+
+def energy_and_partials_spin(n_up, n_dn, s_uu, s_dd, cell, kernel, flavour="DF1", progress=None):
+    """Spin-polarised E_c^nl (the reading in the header) and its partial derivatives with respect
+    to n_up, n_dn, sigma_uu = |grad n_up|^2 and sigma_dd = |grad n_dn|^2 per point, with the
+    normalisation of energy_and_partials (dE/d(value at point j) = derivative_j * Omega/N).
+    Returns (E, dedn_up, dedn_dn, dedsigma_uu, dedsigma_dd)."""
+    steps = _Steps(progress)
+    fields = [np.asarray(a, dtype=np.float64) for a in (n_up, n_dn, s_uu, s_dd)]
+    grid = fields[0].shape
+    check_inputs(grid, cell, fields[0] + fields[1], fields[2] + fields[3])
+    table, kmax, qmesh = _as_table(kernel)
+    omega = float(np.linalg.det(np.asarray(cell, dtype=np.float64)))
+    knorm = gvector_norms(grid, cell)
+    if np.max(knorm) >= kmax:
+        raise ValueError("grid reaches |G| >= kmax of the kernel table")
+    theta, dtheta = theta_and_derivatives_spin(*fields, qmesh, ZAB[flavour])       # step 1
+    steps.done("q0 + theta")
+    E, F, _, _ = _nonlocal_fields(theta, knorm, table, kmax, omega, steps)         # steps 2-4
+    parts = [np.sum(F * d, axis=0) for d in dtheta]                                 # step 5
+    steps.done("derivatives")
+    return (E, *parts)
 
 
 def energy_real_space(theta, F, cell):
