@@ -160,6 +160,34 @@ vdwxc_status vdwxc_calculate_async(vdwxc_handle h, const double* n, const double
  * handle's work memory, so it is ordered with the handle's other calls by the stream. */
 vdwxc_status vdwxc_calculate_lda_async(vdwxc_handle h, const double* n, double* v, double* energy_dev);
 
+/* Spin-polarised vdW-DF (paper Sec. 7 announces the variant; the paper prints only the spin-paired
+ * q0, so the spin q0 here is a stated reading): from the spin densities n_up, n_dn and
+ * sigma_uu = |grad n_up|^2, sigma_dd = |grad n_dn|^2 (device, [N1][N2][N3] each) compute E_c^nl with
+ * theta_a = n p_a(q0) for the total density n = n_up + n_dn (Sec. 2) and
+ *   q0 = sum_s [(n_s/n) k_s - (Z_ab/36) sigma_ss / (n n_s k_s)] - (4 pi/3) eps_c(r_s, zeta),
+ * k_s = (6 pi^2 n_s)^(1/3): the appendix's gradient-corrected LDA exchange spin-scaled
+ * (E_x[n_up, n_dn] = (E_x[2 n_up] + E_x[2 n_dn])/2) and the spin-resolved Perdew-Wang 1992 correlation
+ * (the appendix's eps_c(r_s, 0) with the published fits of eps_c(r_s, 1) and the spin stiffness);
+ * saturation, clamp and vacuum as spin-paired, spin densities below 1e-30 (or negative) taken as
+ * zero.  At n_up = n_dn it is the spin-paired functional (dedn_up = dedn_dn = dedn, dedsigma_ss =
+ * 2 dedsigma).  Writes the partial derivatives dE/dn_up, dE/dn_dn, dE/dsigma_uu, dE/dsigma_dd per point
+ * (device, [N1][N2][N3] each, normalised as in vdwxc_calculate) and the energy to the device double
+ * energy_dev.  The four outputs serve as scratch during the call (they hold n and the equivalent
+ * spin-paired sigma between the passes); they must not overlap each other or the inputs
+ * (VDWXC_EINVAL).  Arithmetic of the conversions is FP64 in both precisions; the pipeline in
+ * between runs in the handle's precision.  A NaN input gives NaN in the energy (the synchronous
+ * form returns VDWXC_EINVAL).  Asynchronous on the handle's stream, in its work memory. */
+vdwxc_status vdwxc_calculate_spin_async(vdwxc_handle h, const double* n_up, const double* n_dn,
+                                        const double* sigma_uu, const double* sigma_dd, double* dedn_up,
+                                        double* dedn_dn, double* dedsigma_uu, double* dedsigma_dd,
+                                        double* energy_dev);
+
+/* As vdwxc_calculate_spin_async with the energy written to *energy_host (a host pointer);
+ * synchronises the handle's stream. */
+vdwxc_status vdwxc_calculate_spin(vdwxc_handle h, const double* n_up, const double* n_dn, const double* sigma_uu,
+                                  const double* sigma_dd, double* dedn_up, double* dedn_dn, double* dedsigma_uu,
+                                  double* dedsigma_dd, double* energy_host);
+
 /* Device memory a handle for this grid allocates for its work buffers (excluding the shared
  * tables), for admission control, with the paper's N_alpha = 20 q-mesh points; 0 if the grid or
  * precision is invalid.  Host-only. */
@@ -198,7 +226,8 @@ typedef enum {
   VDWXC_STAGE_DIV_Y = 9,        /* z, y, x (the x pass subtracts it from the potential) */
   VDWXC_STAGE_DIV_X = 10,
   VDWXC_STAGE_LDA = 11,         /* LDA correlation pass (vdwxc_calculate_lda_async) */
-  VDWXC_NUM_STAGES = 12
+  VDWXC_STAGE_SPIN = 12,        /* spin conversions before and after the pipeline (vdwxc_calculate_spin*) */
+  VDWXC_NUM_STAGES = 13
 } vdwxc_stage;
 
 /* Per-stage timing with HIP events recorded on the handle's stream around every kernel launch

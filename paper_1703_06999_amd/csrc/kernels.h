@@ -1211,6 +1211,152 @@ __global__ void __launch_bounds__(kLdaThreads) k_lda_energy(const double* __rest
   if (tid == 0) energy[0] = tot * scale;
 }
 
+// ---- spin polarisation (the variant Sec. 7 announces) -----------------------------------------
+// The paper prints only the spin-paired q0.  Spin-polarised q0 here: the gradient-corrected LDA
+// exchange of the appendix spin-scaled, E_x[n_up, n_dn] = (E_x[2 n_up] + E_x[2 n_dn]) / 2, plus the
+// spin-resolved PW92 correlation eps_c(r_s, zeta):
+//   q0 = sum_s [ (n_s/n) k_s - (Z_ab/36) sigma_ss / (n n_s k_s) ] - (4 pi/3) eps_c(r_s, zeta)
+// with k_s = (6 pi^2 n_s)^(1/3), n = n_up + n_dn, zeta = (n_up - n_dn)/n; a spin density below the
+// vacuum threshold (or negative) counts as zero.  theta_a = n p_a(q0) as spin-paired.
+//
+// The spin-paired pipeline runs unchanged on (n, sigma_eff): sigma_eff is the sigma for which the
+// spin-paired q0 formula gives the spin-polarised q0 (the gradient term is linear in sigma, so it
+// is one division).  q0 then carries the same saturation, clamp and spline state, and from the
+// pipeline's dE/dn|sigma_eff = P + n h' dx_u/dn D and dE/dsigma_eff = n h' dx_u/dsigma D
+// (P = sum F p, D = sum F p', h' the saturation slope, x_u the spin-paired unsaturated q0):
+//   dE/dn_s       = dE/dn + (dE/dsigma_eff / dx_u/dsigma) (dx/dn_s - dx_u/dn)
+//   dE/dsigma_ss  = (dE/dsigma_eff / dx_u/dsigma) dx/dsigma_ss
+// exactly (dx_u/dsigma = -Z_ab/(36 k_F n^2) is never zero).
+
+// Perdew-Wang 1992 fits of eps_c(r_s, 1) and of -alpha_c(r_s) (the spin stiffness), in the form of
+// the appendix's eps_c(r_s, 0); f''(0) of the spin interpolation f(zeta)
+constexpr double kFerro[6] = {0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517};
+constexpr double kStiff[6] = {0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671};
+constexpr double kFzz0 = 1.709921;
+
+// G(r_s) = -2A (1 + alpha1 r_s) ln[1 + 1/(2A (b1 r_s^1/2 + b2 r_s + b3 r_s^3/2 + b4 r_s^2))], dG/dr_s
+__device__ __forceinline__ void pw92_fit(const double (&c)[6], double rs, double sq, double& G, double& dG) {
+  const double A = c[0];
+  const double Q = 2.0 * A * (c[2] * sq + c[3] * rs + c[4] * rs * sq + c[5] * rs * rs);
+  const double dQ = 2.0 * A * (0.5 * c[2] / sq + c[3] + 1.5 * c[4] * sq + 2.0 * c[5] * rs);
+  const double lg = log1p(1.0 / Q);
+  G = -2.0 * A * (1.0 + c[1] * rs) * lg;
+  dG = -2.0 * A * c[1] * lg + 2.0 * A * (1.0 + c[1] * rs) * dQ / (Q * (Q + 1.0));
+}
+
+// Unsaturated spin-polarised q0 x and its partials (n_up, n_dn, sigma_uu, sigma_dd) at a point with
+// n = nu + nd >= the vacuum threshold (nu, nd already cut at it), and the spin-paired
+// quantities the conversion needs: k_F, r_s and eps_c(r_s, 0), d eps_c / d r_s.
+struct SpinQ0 {
+  double x, dx[4];
+  double kF, rs, e0, de0;
+};
+__device__ __forceinline__ SpinQ0 spin_q0(double nu, double nd, double su, double sd, double zab) {
+  SpinQ0 r;
+  const double n = nu + nd, inv_n = 1.0 / n;
+  double X = 0.0, dxs[2] = {0.0, 0.0}, dss[2] = {0.0, 0.0};
+  const double ns[2] = {nu, nd}, ss[2] = {su, sd};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (ns[c] > 0.0) {
+      const double k = cbrt(6.0 * kPi * kPi * ns[c]);
+      const double inv_nk = 1.0 / (ns[c] * k);
+      X += ns[c] * inv_n * k - (zab / 36.0) * ss[c] * inv_n * inv_nk;
+      dxs[c] = (4.0 / 3.0) * k * inv_n + (zab / 27.0) * ss[c] * inv_n * inv_nk / ns[c];
+      dss[c] = -(zab / 36.0) * inv_n * inv_nk;
+    }
+  }
+  r.kF = cbrt(3.0 * kPi * kPi * n);
+  r.rs = kRsKf / r.kF;
+  const double sq = sqrt(r.rs);
+  pw92(r.rs, r.e0, r.de0);
+  double e1, de1, ma, dma;
+  pw92_fit(kFerro, r.rs, sq, e1, de1);
+  pw92_fit(kStiff, r.rs, sq, ma, dma);
+  const double ac = -ma, dac = -dma;
+  // a true division: at n_dn = 0 it gives zeta = 1 exactly, where f' holds (1 - zeta)^(1/3) and a
+  // rounded 1 - 2^-53 would add cbrt(1e-16) ~ 5e-6 to it
+  const double z = (nu - nd) / n;
+  const double cu = cbrt(1.0 + z), cd = cbrt(1.0 - z);
+  const double fden = 1.0 / (2.0 * cbrt(2.0) - 2.0);   // 1 / (2^(4/3) - 2)
+  const double f = ((1.0 + z) * cu + (1.0 - z) * cd - 2.0) * fden;
+  const double df = (4.0 / 3.0) * (cu - cd) * fden;
+  const double z3 = z * z * z, z4 = z3 * z;
+  const double ec = r.e0 + ac * f / kFzz0 * (1.0 - z4) + (e1 - r.e0) * f * z4;
+  const double dec_drs = r.de0 + dac * f / kFzz0 * (1.0 - z4) + (de1 - r.de0) * f * z4;
+  const double dec_dz = ac / kFzz0 * (df * (1.0 - z4) - 4.0 * z3 * f) + (e1 - r.e0) * (df * z4 + 4.0 * z3 * f);
+  const double c43 = 4.0 * kPi / 3.0;
+  r.x = X - c43 * ec;
+  const double drs = -r.rs * (1.0 / 3.0) * inv_n;
+  r.dx[0] = dxs[0] - X * inv_n - c43 * (dec_drs * drs + dec_dz * (1.0 - z) * inv_n);
+  r.dx[1] = dxs[1] - X * inv_n - c43 * (dec_drs * drs - dec_dz * (1.0 + z) * inv_n);
+  r.dx[2] = dss[0];
+  r.dx[3] = dss[1];
+  return r;
+}
+
+// the spin densities as the functional takes them: cut at the vacuum threshold (NaN stays NaN)
+__device__ __forceinline__ double spin_channel(double v) { return (v >= kVacuum || v != v) ? v : 0.0; }
+
+constexpr int kSpinThreads = 256, kSpinBlocks = 4096;
+
+// (n_up, n_dn, sigma_uu, sigma_dd) -> (n, sigma_eff) for the spin-paired pipeline.  A NaN input
+// gives NaN in both (the pipeline flags it).
+__global__ void __launch_bounds__(kSpinThreads)
+k_spin_in(const double* __restrict__ nu, const double* __restrict__ nd, const double* __restrict__ su,
+          const double* __restrict__ sd, double* __restrict__ n_out, double* __restrict__ s_out, double zab,
+          long long npts) {
+  for (long long p = (long long)blockIdx.x * kSpinThreads + threadIdx.x; p < npts;
+       p += (long long)gridDim.x * kSpinThreads) {
+    const double a = spin_channel(nu[p]), b = spin_channel(nd[p]), sa = su[p], sb = sd[p];
+    const double n = a + b;
+    double seff = 0.0;
+    if (!(a == a) || !(b == b) || !(sa == sa) || !(sb == sb)) {
+      seff = __builtin_nan("");
+    } else if (n >= kVacuum) {
+      const SpinQ0 q = spin_q0(a, b, sa, sb, zab);
+      seff = (q.kF - (4.0 * kPi / 3.0) * q.e0 - q.x) * (36.0 / zab) * q.kF * n * n;
+    }
+    n_out[p] = n;
+    s_out[p] = seff;
+  }
+}
+
+// The pipeline's dE/dn|sigma_eff (in dnu) and dE/dsigma_eff (in dsu) -> the four spin partials,
+// in place: dnu, dnd (which held n), dsu, dsd (which held sigma_eff).
+__global__ void __launch_bounds__(kSpinThreads)
+k_spin_out(const double* __restrict__ nu, const double* __restrict__ nd, const double* __restrict__ su,
+           const double* __restrict__ sd, double* __restrict__ dnu, double* __restrict__ dnd,
+           double* __restrict__ dsu, double* __restrict__ dsd, double zab, long long npts) {
+  for (long long p = (long long)blockIdx.x * kSpinThreads + threadIdx.x; p < npts;
+       p += (long long)gridDim.x * kSpinThreads) {
+    const double n = dnd[p], seff = dsd[p], den = dnu[p], des = dsu[p];
+    double o[4] = {den, den, 0.0, 0.0};
+    // des = 0 where q0 is saturated or clamped (h' = 0): there dE/dn_s = dE/dn and no sigma
+    // dependence, without forming 0 * (a possibly infinite sigma_eff term)
+    if (n >= kVacuum && seff == seff && des != 0.0) {
+      const double a = spin_channel(nu[p]), b = spin_channel(nd[p]);
+      const SpinQ0 q = spin_q0(a, b, su[p], sd[p], zab);
+      const double inv_n = 1.0 / n, inv_kn2 = inv_n * inv_n / q.kF;
+      // the spin-paired x_u's partials at (n, sigma_eff), as the pipeline's q0 pass forms them
+      const double dxdn_u = (1.0 / 3.0) * q.kF * inv_n + (4.0 * kPi / 9.0) * q.rs * inv_n * q.de0 +
+                            (7.0 * zab / 108.0) * seff * inv_kn2 * inv_n;
+      const double dxds_u = -(zab / 36.0) * inv_kn2;
+      const double g = des / dxds_u;
+      o[0] = den + g * (q.dx[0] - dxdn_u);
+      o[1] = den + g * (q.dx[1] - dxdn_u);
+      o[2] = g * q.dx[2];
+      o[3] = g * q.dx[3];
+    } else if (!(n >= kVacuum) && n == n) {
+      o[0] = o[1] = 0.0;
+    }
+    dnu[p] = o[0];
+    dnd[p] = o[1];
+    dsu[p] = o[2];
+    dsd[p] = o[3];
+  }
+}
+
 // ---- pass 5: inverse z FFT + assembly of dE/dn, dE/dsigma (eqs. dedn, dedsigma) -------------
 // dE/dn = sum_a F_a [p_a + n p_a' dq0/dn],  dE/dsigma = sum_a F_a n p_a' dq0/dsigma, with F_a(r)
 // from the inverse transforms (1/N applied here).  The per-point spline state (b, t, n dq0/dn,

@@ -1032,6 +1032,41 @@ vdwxc_status run_lda(vdwxc_ctx* h, const Work& w, const double* n, double* v, do
   return finish_launch(h);
 }
 
+// Spin-polarised evaluation: (n, sigma_eff) into the dedn_dn / dedsigma_dd outputs, the spin-paired
+// partials pipeline from there into dedn_up / dedsigma_uu, then the conversion to the four spin
+// partials in place (k_spin_in, k_spin_out).
+vdwxc_status run_spin(vdwxc_ctx* h, const Work& w, const double* nu, const double* nd, const double* su,
+                      const double* sd, double* dnu, double* dnd, double* dsu, double* dsd, double* energy_dev) {
+  HIP_TRY(h, hipSetDevice(h->device));
+  const long long N = (long long)h->n1 * h->n2 * h->n3;
+  const int blocks = int(std::min<long long>(kSpinBlocks, (N + kSpinThreads - 1) / kSpinThreads));
+  stage_begin(h, w);
+  hipLaunchKernelGGL(k_spin_in, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, su, sd, dnd, dsd, h->geo.zab, N);
+  stage_end(h, w, VDWXC_STAGE_SPIN);
+  if (vdwxc_status st = run_partials(h, w, dnd, dsd, dnu, dsu, energy_dev); st != VDWXC_OK) return st;
+  stage_begin(h, w);
+  hipLaunchKernelGGL(k_spin_out, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, su, sd, dnu, dnd, dsu, dsd,
+                     h->geo.zab, N);
+  stage_end(h, w, VDWXC_STAGE_SPIN);
+  return finish_launch(h);
+}
+
+// the eight arrays of a spin call: none NULL, the outputs overlapping neither each other nor the
+// inputs (N doubles each)
+vdwxc_status check_spin_arrays(vdwxc_ctx* h, const double* const in[4], double* const out[4]) {
+  const size_t N = size_t(h->n1) * h->n2 * h->n3;
+  for (int i = 0; i < 4; ++i)
+    if (!in[i] || !out[i]) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  auto overlap = [&](const double* a, const double* b) { return a < b + N && b < a + N; };
+  for (int i = 0; i < 4; ++i) {
+    for (int j = 0; j < 4; ++j)
+      if (overlap(out[i], in[j])) return fail(h, VDWXC_EINVAL, "spin outputs must not overlap the inputs");
+    for (int j = i + 1; j < 4; ++j)
+      if (overlap(out[i], out[j])) return fail(h, VDWXC_EINVAL, "spin outputs must not overlap each other");
+  }
+  return VDWXC_OK;
+}
+
 vdwxc_status read_energy(vdwxc_ctx* h, double* energy_host) {
   HIP_TRY(h, hipMemcpyAsync(h->h_energy, h->d_energy, sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipMemcpyAsync(h->h_flag, h->work.flag + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1402,6 +1437,32 @@ vdwxc_status vdwxc_calculate(vdwxc_handle h, const double* n, const double* sigm
   return read_energy(h, energy_host);
 }
 
+vdwxc_status vdwxc_calculate_spin_async(vdwxc_handle h, const double* n_up, const double* n_dn,
+                                        const double* sigma_uu, const double* sigma_dd, double* dedn_up,
+                                        double* dedn_dn, double* dedsigma_uu, double* dedsigma_dd,
+                                        double* energy_dev) {
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
+  const double* in[4] = {n_up, n_dn, sigma_uu, sigma_dd};
+  double* out[4] = {dedn_up, dedn_dn, dedsigma_uu, dedsigma_dd};
+  if (!energy_dev) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  if (vdwxc_status st = check_spin_arrays(h, in, out); st != VDWXC_OK) return st;
+  return run_spin(h, h->work, n_up, n_dn, sigma_uu, sigma_dd, dedn_up, dedn_dn, dedsigma_uu, dedsigma_dd, energy_dev);
+}
+
+vdwxc_status vdwxc_calculate_spin(vdwxc_handle h, const double* n_up, const double* n_dn, const double* sigma_uu,
+                                  const double* sigma_dd, double* dedn_up, double* dedn_dn, double* dedsigma_uu,
+                                  double* dedsigma_dd, double* energy_host) {
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
+  const double* in[4] = {n_up, n_dn, sigma_uu, sigma_dd};
+  double* out[4] = {dedn_up, dedn_dn, dedsigma_uu, dedsigma_dd};
+  if (!energy_host) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  if (vdwxc_status st = check_spin_arrays(h, in, out); st != VDWXC_OK) return st;
+  vdwxc_status st = run_spin(h, h->work, n_up, n_dn, sigma_uu, sigma_dd, dedn_up, dedn_dn, dedsigma_uu, dedsigma_dd,
+                             h->d_energy);
+  if (st != VDWXC_OK) return st;
+  return read_energy(h, energy_host);
+}
+
 vdwxc_status vdwxc_calculate_potential_async(vdwxc_handle h, const double* n, const double* grad_n, double* v,
                                              double* energy_dev) {
   if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
@@ -1465,7 +1526,7 @@ vdwxc_status vdwxc_set_workspace(vdwxc_handle h, void* workspace, size_t bytes) 
 const char* vdwxc_stage_name(int stage) {
   static const char* names[VDWXC_NUM_STAGES] = {
       "theta_zfwd", "y_fwd", "x_contract", "y_inv", "z_assemble", "grad_z", "grad_y",
-      "grad_x", "div_z", "div_y", "div_x", "lda"};
+      "grad_x", "div_z", "div_y", "div_x", "lda", "spin"};
   return (stage >= 0 && stage < VDWXC_NUM_STAGES) ? names[stage] : "?";
 }
 

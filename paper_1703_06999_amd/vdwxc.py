@@ -43,6 +43,8 @@ SIGNATURES = {
     "vdwxc_calculate_potential_async": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                        ctypes.c_void_p]),
     "vdwxc_calculate_lda_async": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "vdwxc_calculate_spin": (ctypes.c_int, [_h] + [ctypes.c_void_p] * 8 + [_dp]),
+    "vdwxc_calculate_spin_async": (ctypes.c_int, [_h] + [ctypes.c_void_p] * 9),
     "vdwxc_calculate_potential_noalloc": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                          ctypes.c_void_p]),
     "vdwxc_workspace_bytes": (ctypes.c_size_t, [_ip, ctypes.c_int]),
@@ -57,7 +59,7 @@ SIGNATURES = {
     "vdwxc_read_timing": (ctypes.c_int, [_h, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "vdwxc_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
 }
-NUM_STAGES = 12
+NUM_STAGES = 13
 
 _lib = None
 
@@ -227,6 +229,30 @@ class Functional:
         self.lda_async(n, v, e)
         torch.cuda.synchronize(n.device)
         return float(e.item()), v
+
+    def spin_async(self, n_up, n_dn, sigma_uu, sigma_dd, outs, energy):
+        """Enqueue the spin-polarised partials evaluation: outs = (dedn_up, dedn_dn, dedsigma_uu,
+        dedsigma_dd) device tensors (distinct from the inputs), energy a 1-element float64 tensor."""
+        self._sync_stream()
+        ins = [self._field(a, k) for a, k in ((n_up, "n_up"), (n_dn, "n_dn"), (sigma_uu, "sigma_uu"),
+                                              (sigma_dd, "sigma_dd"))]
+        os_ = [self._field(a, k) for a, k in zip(outs, ("dedn_up", "dedn_dn", "dedsigma_uu", "dedsigma_dd"))]
+        st = lib().vdwxc_calculate_spin_async(self._h, *ins, *os_, ctypes.c_void_p(energy.data_ptr()))
+        _check(st, self._h)
+
+    def spin(self, n_up, n_dn, sigma_uu, sigma_dd):
+        """(E, dedn_up, dedn_dn, dedsigma_uu, dedsigma_dd) of the spin-polarised functional
+        (vdwxc_calculate_spin); synchronises the stream."""
+        import torch
+        outs = [torch.empty_like(n_up) for _ in range(4)]
+        e = ctypes.c_double(0.0)
+        self._sync_stream()
+        ins = [self._field(a, k) for a, k in ((n_up, "n_up"), (n_dn, "n_dn"), (sigma_uu, "sigma_uu"),
+                                              (sigma_dd, "sigma_dd"))]
+        os_ = [self._field(a, k) for a, k in zip(outs, ("dedn_up", "dedn_dn", "dedsigma_uu", "dedsigma_dd"))]
+        st = lib().vdwxc_calculate_spin(self._h, *ins, *os_, ctypes.byref(e))
+        _check(st, self._h)
+        return (e.value, *outs)
 
     def set_workspace(self, buf):
         """Run later calls in `buf` (a CUDA tensor of at least workspace_bytes(grid, precision, nq)
