@@ -193,6 +193,38 @@ def time_lda(f, n, steps: int, npoints: int):
             "bytes_per_point": 16, "E_c_lda": float(e.item())}
 
 
+def time_spin(f, n, g, steps: int):
+    """The spin-polarised entry on the same density split n_up = 0.6 n, n_dn = 0.4 n (zeta = 0.2,
+    sigma_ss from the same gradient), against the spin-paired partials entry on n: wall time per
+    evaluation, and the two conversion passes from the library's HIP events."""
+    import torch
+    sigma = torch.sum(g * g, dim=0)
+    ins = (0.6 * n, 0.4 * n, 0.36 * sigma, 0.16 * sigma)
+    outs = [torch.empty_like(n) for _ in range(4)]
+    e = torch.zeros(1, dtype=torch.float64, device=n.device)
+    res = {"zeta": 0.2}
+    for label, call in (("partials", lambda: f.calculate_async(n, sigma, outs[0], outs[1], e)),
+                        ("spin", lambda: f.spin_async(*ins, outs, e))):
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        res[f"{label}_ms_per_eval"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    f.enable_timing(True)
+    for _ in range(steps):
+        f.spin_async(*ins, outs, e)
+    ms, cnt = f.read_timing()["spin"]
+    f.enable_timing(False)
+    res["conversion_ms_per_eval"] = round(ms / steps, 4)
+    res["conversion_launches"] = cnt
+    res["E"] = float(e.item())
+    del ins, outs, sigma
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_measurement(kt, count, rate, precision):
     """Poisson stream of `count` energy+potential requests (grids 48..160^3) through the
     continuous-batching server: once with a 64 GB HBM budget, once with the budget capped at 1.25x
@@ -237,6 +269,7 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-qmesh", action="store_true",
                     help="skip the timing of the headline form with a 10-point q-mesh")
+    ap.add_argument("--no-spin", action="store_true", help="skip the spin-polarised entry timing")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--density-cache", default=None,
@@ -275,7 +308,7 @@ def main() -> int:
 
     forms = [args.precision] + ([] if args.no_second_form else [p for p in ("fp64", "fp32") if p != args.precision])
     results = {}
-    lda = None
+    lda = spin = None
     for prec in forms:
         f = vdwxc.Functional(w.grid, w.cell, flavour="DF1", precision=prec, table=kt)
         ms, stages, roof, v, E = time_form(f, n, g, args.steps, args.warmup, w.grid, prec)
@@ -283,6 +316,9 @@ def main() -> int:
         if prec == args.precision:
             lda = time_lda(f, n, args.steps, w.npoints)
             say(f"lda correlation: {lda['ms_avg']:.3f} ms, {lda['GBps']:.0f} GB/s")
+            if not args.no_spin:
+                spin = time_spin(f, n, g, max(2, args.steps // 4))
+                say(f"spin: {spin}")
         f.close()
         results[prec] = dict(ms=ms, stages=stages, roofline=roof, v=v, E=E)
         say(f"{prec}: {ms:.3f} ms/step, {w.npoints / ms * 1e3:.4e} pts/s, E = {E:.12e}, "
@@ -384,6 +420,7 @@ def main() -> int:
         "serving": serve,
         "q_mesh_10": qmesh,
         "lda_correlation": lda,
+        "spin_polarised": spin,
     }
     print(json.dumps(out), flush=True)
     return 0
