@@ -20,7 +20,7 @@ Steps (Sec. 3, Table 1, and the enumerated procedure of Sec. 3):
   6. dE/dn, dE/dsigma                                           (Sec. 2, eqs. dedn and dedsigma)
 and, beside the nonlocal path, the semilocal LDA correlation E_c^LDA, v_c^LDA of eq. 1's split
 (PW92, appendix), and the spin-polarised variant that Sec. 7 announces (q0 from the two spin
-densities; steps 2-5 unchanged).
+densities; steps 2-5 unchanged; the two potentials as the spin-paired one, per spin).
 
 Readings where the paper is silent or garbled (each also listed in the design notes):
   * r_s = (3/(4 pi n))^{1/3}, the Wigner-Seitz radius (the appendix prints r_s^3 = 4 pi n/3,
@@ -641,3 +641,20 @@ def potential(n, cell, kernel, grad=None, flavour="DF1", progress=None):
     div = sum(spectral_derivative(2.0 * dedsigma * g[i], cell, i) for i in range(3))
     steps.done("divergence")
     return E, dedn - div, dedn, dedsigma
+
+
+def potential_spin(n_up, n_dn, grad_up, grad_dn, cell, kernel, flavour="DF1", progress=None):
+    """Spin-polarised potentials v_s = dE/dn_s|_sigma - div(2 dE/dsigma_ss grad n_s), s = up, dn
+    (the spin functional of energy_and_partials_spin depends on sigma_ss = |grad n_s|^2 only), with
+    the supplied gradients [3][...] and the spectral divergence of ``potential``.
+    Returns (E, v_up, v_dn)."""
+    steps = _Steps(progress)
+    g = [np.asarray(x, dtype=np.float64) for x in (grad_up, grad_dn)]
+    sig = [np.sum(x * x, axis=0) for x in g]
+    E, dnu, dnd, dsu, dsd = energy_and_partials_spin(n_up, n_dn, sig[0], sig[1], cell, kernel, flavour,
+                                                    progress=progress)
+    steps.t = time.perf_counter()
+    v = [dn - sum(spectral_derivative(2.0 * ds * gs[i], cell, i) for i in range(3))
+         for dn, ds, gs in ((dnu, dsu, g[0]), (dnd, dsd, g[1]))]
+    steps.done("divergence")
+    return E, v[0], v[1]

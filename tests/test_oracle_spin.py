@@ -191,3 +191,43 @@ def test_exchanging_the_spins_exchanges_the_outputs():
     assert E2 == pytest.approx(E, rel=1e-14)
     for x, y in ((a, b2), (b, a2), (c, d2), (d, c2)):
         assert np.max(np.abs(x - y)) <= 1e-13 * np.max(np.abs(x))
+
+
+def test_potentials_at_equal_spins_are_the_spin_paired_potential():
+    _, cell, n, _ = paired_grid(3)
+    n = n + 1e-3
+    g = vdwdf.spectral_gradient(n, cell)
+    E, v, _, _ = vdwdf.potential(n, cell, KT, grad=g)
+    Es, vu, vd = vdwdf.potential_spin(n / 2, n / 2, g / 2, g / 2, cell, KT)
+    assert Es == pytest.approx(E, rel=1e-13)
+    scale = np.max(np.abs(v))
+    assert np.max(np.abs(vu - v)) <= 1e-11 * scale and np.max(np.abs(vd - v)) <= 1e-11 * scale
+
+
+def test_potentials_are_the_derivatives_of_the_energy():
+    # with the spectral gradients of n_up and n_dn, E is a function of the two densities alone and
+    # dE/dn_s(r_j) = v_s(r_j) Omega/N (Richardson central differences)
+    cell, (nu, nd, _, _) = polarised_inputs(12)
+    nd = nd + 1e-3          # keep both spins present, so the spectral gradients stay smooth in n
+    dV = abs(np.linalg.det(cell)) / nu.size
+
+    def energy(a, b):
+        return vdwdf.potential_spin(a, b, vdwdf.spectral_gradient(a, cell), vdwdf.spectral_gradient(b, cell),
+                                    cell, KT)[0]
+    _, vu, vd = vdwdf.potential_spin(nu, nd, vdwdf.spectral_gradient(nu, cell), vdwdf.spectral_gradient(nd, cell),
+                                     cell, KT)
+    rng = np.random.default_rng(13)
+    for s, v in ((0, vu), (1, vd)):
+        for j in rng.choice(nu.size, 3, replace=False):
+            base = (nu, nd)[s]
+            h = 1e-3 * base.flat[j]
+
+            def d(step):
+                up, dn = base.copy(), base.copy()
+                up.flat[j] += step
+                dn.flat[j] -= step
+                if s == 0:
+                    return (energy(up, nd) - energy(dn, nd)) / (2 * step)
+                return (energy(nu, up) - energy(nu, dn)) / (2 * step)
+            fd = (4.0 * d(h / 2) - d(h)) / 3.0
+            assert fd == pytest.approx(v.flat[j] * dV, rel=2e-5), (s, j)
