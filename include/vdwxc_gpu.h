@@ -188,6 +188,25 @@ vdwxc_status vdwxc_calculate_spin(vdwxc_handle h, const double* n_up, const doub
                                   const double* sigma_dd, double* dedn_up, double* dedn_dn, double* dedsigma_uu,
                                   double* dedsigma_dd, double* energy_host);
 
+/* Spin-polarised potentials v_up = dE/dn_up|sigma - div(2 dE/dsigma_uu grad n_up) and the same for
+ * n_dn: the functional derivatives of the spin-polarised E of vdwxc_calculate_spin_async, which
+ * depends on the gradients only through sigma_uu = |grad n_up|^2 and sigma_dd = |grad n_dn|^2 (paper
+ * Sec. 2's potential, per spin).  grad_up, grad_dn (device, [3][N1][N2][N3] each, Cartesian
+ * components) are the caller's gradients and are required (NULL: VDWXC_EINVAL); the divergences are
+ * spectral with every Nyquist frequency dropped, as in vdwxc_calculate_potential.  Writes v_up, v_dn
+ * (device, [N1][N2][N3]; v_dn serves as scratch for n during the call; neither may overlap the
+ * inputs or the other, VDWXC_EINVAL) and the energy to the device double energy_dev.  Runs in the
+ * handle's work memory, asynchronously on its stream. */
+vdwxc_status vdwxc_calculate_spin_potential_async(vdwxc_handle h, const double* n_up, const double* n_dn,
+                                                  const double* grad_up, const double* grad_dn, double* v_up,
+                                                  double* v_dn, double* energy_dev);
+
+/* As vdwxc_calculate_spin_potential_async with the energy written to *energy_host (a host pointer);
+ * synchronises the handle's stream; a NaN input gives VDWXC_EINVAL. */
+vdwxc_status vdwxc_calculate_spin_potential(vdwxc_handle h, const double* n_up, const double* n_dn,
+                                            const double* grad_up, const double* grad_dn, double* v_up, double* v_dn,
+                                            double* energy_host);
+
 /* Device memory a handle for this grid allocates for its work buffers (excluding the shared
  * tables), for admission control, with the paper's N_alpha = 20 q-mesh points; 0 if the grid or
  * precision is invalid.  Host-only. */

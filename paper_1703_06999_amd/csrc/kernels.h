@@ -1300,15 +1300,29 @@ __device__ __forceinline__ double spin_channel(double v) { return (v >= kVacuum 
 
 constexpr int kSpinThreads = 256, kSpinBlocks = 4096;
 
-// (n_up, n_dn, sigma_uu, sigma_dd) -> (n, sigma_eff) for the spin-paired pipeline.  A NaN input
-// gives NaN in both (the pipeline flags it).
+// sigma_ss at point p: given (FROM_GRAD false), or |grad n_s|^2 from the gradient [3][npts]
+template <bool FROM_GRAD>
+__device__ __forceinline__ double spin_sigma(const double* __restrict__ s, long long p, long long npts) {
+  if constexpr (FROM_GRAD) {
+    const double a = s[p], b = s[npts + p], c = s[2 * npts + p];
+    return a * a + b * b + c * c;
+  } else {
+    return s[p];
+  }
+}
+
+// (n_up, n_dn, sigma_uu, sigma_dd) -> (n, sigma_eff) for the spin-paired pipeline (su, sd: the
+// sigmas, or with FROM_GRAD the gradients of n_up, n_dn).  A NaN input gives NaN in both (the
+// pipeline flags it).
+template <bool FROM_GRAD>
 __global__ void __launch_bounds__(kSpinThreads)
 k_spin_in(const double* __restrict__ nu, const double* __restrict__ nd, const double* __restrict__ su,
           const double* __restrict__ sd, double* __restrict__ n_out, double* __restrict__ s_out, double zab,
           long long npts) {
   for (long long p = (long long)blockIdx.x * kSpinThreads + threadIdx.x; p < npts;
        p += (long long)gridDim.x * kSpinThreads) {
-    const double a = spin_channel(nu[p]), b = spin_channel(nd[p]), sa = su[p], sb = sd[p];
+    const double a = spin_channel(nu[p]), b = spin_channel(nd[p]);
+    const double sa = spin_sigma<FROM_GRAD>(su, p, npts), sb = spin_sigma<FROM_GRAD>(sd, p, npts);
     const double n = a + b;
     double seff = 0.0;
     if (!(a == a) || !(b == b) || !(sa == sa) || !(sb == sb)) {
@@ -1323,7 +1337,8 @@ k_spin_in(const double* __restrict__ nu, const double* __restrict__ nd, const do
 }
 
 // The pipeline's dE/dn|sigma_eff (in dnu) and dE/dsigma_eff (in dsu) -> the four spin partials,
-// in place: dnu, dnd (which held n), dsu, dsd (which held sigma_eff).
+// in place: dnu, dnd (which held n), dsu, dsd (which held sigma_eff).  su, sd as for k_spin_in.
+template <bool FROM_GRAD>
 __global__ void __launch_bounds__(kSpinThreads)
 k_spin_out(const double* __restrict__ nu, const double* __restrict__ nd, const double* __restrict__ su,
            const double* __restrict__ sd, double* __restrict__ dnu, double* __restrict__ dnd,
@@ -1336,7 +1351,7 @@ k_spin_out(const double* __restrict__ nu, const double* __restrict__ nd, const d
     // dependence, without forming 0 * (a possibly infinite sigma_eff term)
     if (n >= kVacuum && seff == seff && des != 0.0) {
       const double a = spin_channel(nu[p]), b = spin_channel(nd[p]);
-      const SpinQ0 q = spin_q0(a, b, su[p], sd[p], zab);
+      const SpinQ0 q = spin_q0(a, b, spin_sigma<FROM_GRAD>(su, p, npts), spin_sigma<FROM_GRAD>(sd, p, npts), zab);
       const double inv_n = 1.0 / n, inv_kn2 = inv_n * inv_n / q.kF;
       // the spin-paired x_u's partials at (n, sigma_eff), as the pipeline's q0 pass forms them
       const double dxdn_u = (1.0 / 3.0) * q.kF * inv_n + (4.0 * kPi / 9.0) * q.rs * inv_n * q.de0 +

@@ -1041,14 +1041,64 @@ vdwxc_status run_spin(vdwxc_ctx* h, const Work& w, const double* nu, const doubl
   const long long N = (long long)h->n1 * h->n2 * h->n3;
   const int blocks = int(std::min<long long>(kSpinBlocks, (N + kSpinThreads - 1) / kSpinThreads));
   stage_begin(h, w);
-  hipLaunchKernelGGL(k_spin_in, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, su, sd, dnd, dsd, h->geo.zab, N);
+  hipLaunchKernelGGL(k_spin_in<false>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, su, sd, dnd, dsd,
+                     h->geo.zab, N);
   stage_end(h, w, VDWXC_STAGE_SPIN);
   if (vdwxc_status st = run_partials(h, w, dnd, dsd, dnu, dsu, energy_dev); st != VDWXC_OK) return st;
   stage_begin(h, w);
-  hipLaunchKernelGGL(k_spin_out, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, su, sd, dnu, dnd, dsu, dsd,
-                     h->geo.zab, N);
+  hipLaunchKernelGGL(k_spin_out<false>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, su, sd, dnu, dnd,
+                     dsu, dsd, h->geo.zab, N);
   stage_end(h, w, VDWXC_STAGE_SPIN);
   return finish_launch(h);
+}
+
+// Spin-polarised potentials: as run_spin with sigma_ss taken from the gradients, (n, sigma_eff) in
+// v_dn and the work memory's gradient buffer, the pipeline's partials in v_up and S, the spin
+// partials converted in place (dE/dsigma_uu in S, dE/dsigma_dd in G), then one spectral divergence
+// per spin: v_s = dE/dn_s - div(2 dE/dsigma_ss grad n_s).
+template <typename T>
+void enqueue_spin_potential(vdwxc_ctx* h, const Work& w, const double* nu, const double* nd, const double* gu,
+                            const double* gd, double* vu, double* vd, double* energy_dev, int blocks) {
+  const long long N = (long long)h->n1 * h->n2 * h->n3;
+  stage_begin(h, w);
+  hipLaunchKernelGGL(k_spin_in<true>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, gu, gd, vd, w.G,
+                     h->geo.zab, N);
+  stage_end(h, w, VDWXC_STAGE_SPIN);
+  enqueue_main<T>(h, w, vd, w.G, false, vu, w.S, energy_dev);
+  stage_begin(h, w);
+  hipLaunchKernelGGL(k_spin_out<true>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, gu, gd, vu, vd, w.S,
+                     w.G, h->geo.zab, N);
+  stage_end(h, w, VDWXC_STAGE_SPIN);
+  enqueue_divergence<T>(h, w, w.S, gu, vu);
+  enqueue_divergence<T>(h, w, w.G, gd, vd);
+}
+
+vdwxc_status run_spin_potential(vdwxc_ctx* h, const Work& w, const double* nu, const double* nd, const double* gu,
+                                const double* gd, double* vu, double* vd, double* energy_dev) {
+  HIP_TRY(h, hipSetDevice(h->device));
+  const long long N = (long long)h->n1 * h->n2 * h->n3;
+  const int blocks = int(std::min<long long>(kSpinBlocks, (N + kSpinThreads - 1) / kSpinThreads));
+  if (h->precision == VDWXC_FP64)
+    enqueue_spin_potential<double>(h, w, nu, nd, gu, gd, vu, vd, energy_dev, blocks);
+  else
+    enqueue_spin_potential<float>(h, w, nu, nd, gu, gd, vu, vd, energy_dev, blocks);
+  return finish_launch(h);
+}
+
+// the arrays of a spin potential call: none NULL; v_up, v_dn overlapping neither each other nor the
+// densities (N doubles) and gradients (3N)
+vdwxc_status check_spin_potential_arrays(vdwxc_ctx* h, const double* nu, const double* nd, const double* gu,
+                                         const double* gd, double* vu, double* vd) {
+  const size_t N = size_t(h->n1) * h->n2 * h->n3;
+  if (!nu || !nd || !vu || !vd) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  if (!gu || !gd) return fail(h, VDWXC_EINVAL, "the spin potential needs the gradients of n_up and n_dn");
+  auto overlap = [](const double* a, size_t na, const double* b, size_t nb) { return a < b + nb && b < a + na; };
+  for (double* v : {vu, vd}) {
+    if (overlap(v, N, nu, N) || overlap(v, N, nd, N) || overlap(v, N, gu, 3 * N) || overlap(v, N, gd, 3 * N))
+      return fail(h, VDWXC_EINVAL, "spin outputs must not overlap the inputs");
+  }
+  if (overlap(vu, N, vd, N)) return fail(h, VDWXC_EINVAL, "spin outputs must not overlap each other");
+  return VDWXC_OK;
 }
 
 // the eight arrays of a spin call: none NULL, the outputs overlapping neither each other nor the
@@ -1459,6 +1509,28 @@ vdwxc_status vdwxc_calculate_spin(vdwxc_handle h, const double* n_up, const doub
   if (vdwxc_status st = check_spin_arrays(h, in, out); st != VDWXC_OK) return st;
   vdwxc_status st = run_spin(h, h->work, n_up, n_dn, sigma_uu, sigma_dd, dedn_up, dedn_dn, dedsigma_uu, dedsigma_dd,
                              h->d_energy);
+  if (st != VDWXC_OK) return st;
+  return read_energy(h, energy_host);
+}
+
+vdwxc_status vdwxc_calculate_spin_potential_async(vdwxc_handle h, const double* n_up, const double* n_dn,
+                                                  const double* grad_up, const double* grad_dn, double* v_up,
+                                                  double* v_dn, double* energy_dev) {
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
+  if (!energy_dev) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  if (vdwxc_status st = check_spin_potential_arrays(h, n_up, n_dn, grad_up, grad_dn, v_up, v_dn); st != VDWXC_OK)
+    return st;
+  return run_spin_potential(h, h->work, n_up, n_dn, grad_up, grad_dn, v_up, v_dn, energy_dev);
+}
+
+vdwxc_status vdwxc_calculate_spin_potential(vdwxc_handle h, const double* n_up, const double* n_dn,
+                                            const double* grad_up, const double* grad_dn, double* v_up, double* v_dn,
+                                            double* energy_host) {
+  if (vdwxc_status st0 = check_work(h); st0 != VDWXC_OK) return st0;
+  if (!energy_host) return fail(h, VDWXC_EINVAL, "array arguments must not be NULL");
+  if (vdwxc_status st = check_spin_potential_arrays(h, n_up, n_dn, grad_up, grad_dn, v_up, v_dn); st != VDWXC_OK)
+    return st;
+  vdwxc_status st = run_spin_potential(h, h->work, n_up, n_dn, grad_up, grad_dn, v_up, v_dn, h->d_energy);
   if (st != VDWXC_OK) return st;
   return read_energy(h, energy_host);
 }

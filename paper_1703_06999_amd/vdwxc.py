@@ -45,6 +45,8 @@ SIGNATURES = {
     "vdwxc_calculate_lda_async": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "vdwxc_calculate_spin": (ctypes.c_int, [_h] + [ctypes.c_void_p] * 8 + [_dp]),
     "vdwxc_calculate_spin_async": (ctypes.c_int, [_h] + [ctypes.c_void_p] * 9),
+    "vdwxc_calculate_spin_potential": (ctypes.c_int, [_h] + [ctypes.c_void_p] * 6 + [_dp]),
+    "vdwxc_calculate_spin_potential_async": (ctypes.c_int, [_h] + [ctypes.c_void_p] * 7),
     "vdwxc_calculate_potential_noalloc": (ctypes.c_int, [_h, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                          ctypes.c_void_p]),
     "vdwxc_workspace_bytes": (ctypes.c_size_t, [_ip, ctypes.c_int]),
@@ -253,6 +255,27 @@ class Functional:
         st = lib().vdwxc_calculate_spin(self._h, *ins, *os_, ctypes.byref(e))
         _check(st, self._h)
         return (e.value, *outs)
+
+    def spin_potential_async(self, n_up, n_dn, grad_up, grad_dn, v_up, v_dn, energy):
+        """Enqueue the spin-polarised potentials (vdwxc_calculate_spin_potential_async)."""
+        self._sync_stream()
+        st = lib().vdwxc_calculate_spin_potential_async(
+            self._h, self._field(n_up, "n_up"), self._field(n_dn, "n_dn"), self._field(grad_up, "grad_up", 3),
+            self._field(grad_dn, "grad_dn", 3), self._field(v_up, "v_up"), self._field(v_dn, "v_dn"),
+            ctypes.c_void_p(energy.data_ptr()))
+        _check(st, self._h)
+
+    def spin_potential(self, n_up, n_dn, grad_up, grad_dn):
+        """(E, v_up, v_dn) of the spin-polarised functional; synchronises the stream."""
+        import torch
+        v_up, v_dn = torch.empty_like(n_up), torch.empty_like(n_up)
+        e = ctypes.c_double(0.0)
+        self._sync_stream()
+        st = lib().vdwxc_calculate_spin_potential(
+            self._h, self._field(n_up, "n_up"), self._field(n_dn, "n_dn"), self._field(grad_up, "grad_up", 3),
+            self._field(grad_dn, "grad_dn", 3), self._field(v_up, "v_up"), self._field(v_dn, "v_dn"), ctypes.byref(e))
+        _check(st, self._h)
+        return e.value, v_up, v_dn
 
     def set_workspace(self, buf):
         """Run later calls in `buf` (a CUDA tensor of at least workspace_bytes(grid, precision, nq)

@@ -165,6 +165,8 @@ def test_null_handle_calls():
     assert L.vdwxc_set_workspace(None, None, 0) == vdwxc.ESTATE
     assert L.vdwxc_calculate_spin(None, *([None] * 8), ctypes.byref(e)) == vdwxc.ESTATE
     assert L.vdwxc_calculate_spin_async(None, *([None] * 9)) == vdwxc.ESTATE
+    assert L.vdwxc_calculate_spin_potential(None, *([None] * 6), ctypes.byref(e)) == vdwxc.ESTATE
+    assert L.vdwxc_calculate_spin_potential_async(None, *([None] * 7)) == vdwxc.ESTATE
     h = ctypes.c_void_p()
     assert L.vdwxc_finalize(ctypes.byref(h)) == vdwxc.ESTATE
 

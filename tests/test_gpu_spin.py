@@ -134,3 +134,86 @@ def test_spin_argument_checks(dev):
         assert np.isfinite(E)
     finally:
         f.close()
+
+
+def polarised_with_gradients(grid, length, seed):
+    """(n_up, n_dn, grad_up, grad_dn) as float64 CPU tensors (the densities of `polarised`)."""
+    nu, gu = inputs.small_slater(grid, length, 4, seed, floor=2e-4)
+    nd, gd = inputs.small_slater(grid, length, 3, seed + 50, floor=1e-4)
+    nd, gd = 0.7 * nd, 0.7 * gd
+    nd[:, :, : max(1, grid[2] // 6)] = 0.0
+    gd[:, :, :, : max(1, grid[2] // 6)] = 0.0
+    return nu, nd, gu, gd
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("grid,length,seed", [CASES[0], CASES[2]],
+                         ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else str(v))
+def test_spin_potential_matches_oracle(dev, precision, grid, length, seed):
+    """v_up, v_dn against the oracle's spin potentials: FP64 E <= 1e-10 relative and each v <= 1e-10
+    of its max-norm; FP32_MIXED E <= 1e-5 and v <= 1e-4 of its max-norm (n >= 1e-6 everywhere here)."""
+    from paper_1703_06999_amd import vdwxc
+    say(f"[spin potential] grid {grid} L {length} seed {seed} {precision}")
+    nu, nd, gu, gd = polarised_with_gradients(grid, length, seed)
+    cell = inputs.cubic_cell(length)
+    E_ref, vu_ref, vd_ref = vdwdf.potential_spin(nu.numpy(), nd.numpy(), gu.numpy(), gd.numpy(), cell, KT)
+    f = vdwxc.Functional(grid, cell, flavour="DF1", precision=precision, table=KT)
+    try:
+        E, vu, vd = f.spin_potential(nu.to(dev), nd.to(dev), gu.to(dev), gd.to(dev))
+    finally:
+        f.close()
+    tol = TOL[precision]
+    de = abs(E - E_ref) / abs(E_ref)
+    say(f"    E {E:.15e} oracle {E_ref:.15e} rel {de:.2e}")
+    assert de <= tol["e"]
+    for name, got, want in (("v_up", vu, vu_ref), ("v_dn", vd, vd_ref)):
+        err = float(np.max(np.abs(got.cpu().numpy() - want))) / float(np.max(np.abs(want)))
+        say(f"    {name}: max-norm rel {err:.2e}")
+        assert err <= tol["n"], (name, err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_spin_potential_at_equal_spins_is_the_potential(dev, precision):
+    from paper_1703_06999_amd import vdwxc
+    grid, length = (24, 20, 512), 46.0
+    n, g = inputs.small_slater(grid, length, 5, 9, floor=1e-4, device="cuda")
+    f = vdwxc.Functional(grid, inputs.cubic_cell(length), flavour="DF1", precision=precision, table=KT)
+    try:
+        E, v = f.potential(n, g)
+        Es, vu, vd = f.spin_potential(0.5 * n, 0.5 * n, 0.5 * g, 0.5 * g)
+    finally:
+        f.close()
+    de = abs(Es - E) / abs(E)
+    bound = 1e-10 if precision == "fp64" else 1e-5
+    say(f"[equal spins, potential {precision}] E rel {de:.2e}")
+    assert de <= 1e-13
+    for name, got in (("v_up", vu), ("v_dn", vd)):
+        err = float(torch.max(torch.abs(got - v)) / torch.max(torch.abs(v)))
+        say(f"    {name}: max-norm rel {err:.2e}")
+        assert err <= bound, (name, err)
+
+
+def test_spin_potential_argument_checks(dev):
+    from paper_1703_06999_amd import vdwxc
+    grid = (8, 8, 8)
+    f = vdwxc.Functional(grid, inputs.cubic_cell(6.0), precision="fp64", table=KT)
+    try:
+        nu = torch.full(grid, 0.1, dtype=torch.float64, device=dev)
+        nd = torch.full(grid, 0.05, dtype=torch.float64, device=dev)
+        g = torch.zeros((3,) + grid, dtype=torch.float64, device=dev)
+        vu, vd = torch.empty_like(nu), torch.empty_like(nu)
+        e = torch.zeros(1, dtype=torch.float64, device=dev)
+        with pytest.raises(vdwxc.VdwxcError, match="overlap the inputs"):
+            f.spin_potential_async(nu, nd, g, g, vu, g[1], e)
+        with pytest.raises(vdwxc.VdwxcError, match="overlap each other"):
+            f.spin_potential_async(nu, nd, g, g, vu, vu, e)
+        L = vdwxc.lib()
+        args = [ctypes.c_void_p(t.data_ptr()) for t in (nu, nd, g, g, vu, vd, e)]
+        args[3] = ctypes.c_void_p(0)
+        assert L.vdwxc_calculate_spin_potential_async(f._h, *args) == vdwxc.EINVAL
+        assert "gradients" in L.vdwxc_last_error(f._h).decode()
+        # a uniform polarised gas: no gradient, so v_s = dE/dn_s, and the call still works
+        E, vu, vd = f.spin_potential(nu, nd, g, g)
+        assert np.isfinite(E) and float(torch.std(vu)) <= 1e-12 * float(torch.max(torch.abs(vu)))
+    finally:
+        f.close()
