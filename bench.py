@@ -194,17 +194,16 @@ def time_lda(f, n, steps: int, npoints: int):
 
 
 def time_spin(f, n, g, steps: int):
-    """The spin-polarised entry on the same density split n_up = 0.6 n, n_dn = 0.4 n (zeta = 0.2,
-    sigma_ss from the same gradient), against the spin-paired partials entry on n: wall time per
-    evaluation, and the two conversion passes from the library's HIP events."""
+    """The spin-polarised potential entry on the same density split n_up = 0.6 n, n_dn = 0.4 n
+    (zeta = 0.2, gradients split alike), against the spin-paired potential entry on n: wall time per
+    evaluation, and the two spin conversion passes from the library's HIP events."""
     import torch
-    sigma = torch.sum(g * g, dim=0)
-    ins = (0.6 * n, 0.4 * n, 0.36 * sigma, 0.16 * sigma)
-    outs = [torch.empty_like(n) for _ in range(4)]
+    ins = (0.6 * n, 0.4 * n, 0.6 * g, 0.4 * g)
+    vu, vd, v = torch.empty_like(n), torch.empty_like(n), torch.empty_like(n)
     e = torch.zeros(1, dtype=torch.float64, device=n.device)
-    res = {"zeta": 0.2}
-    for label, call in (("partials", lambda: f.calculate_async(n, sigma, outs[0], outs[1], e)),
-                        ("spin", lambda: f.spin_async(*ins, outs, e))):
+    res = {"zeta": 0.2, "entry": "vdwxc_calculate_spin_potential_async against vdwxc_calculate_potential_async"}
+    for label, call in (("spin_paired", lambda: f.potential_async(n, g, v, e)),
+                        ("spin", lambda: f.spin_potential_async(*ins, vu, vd, e))):
         call()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -214,13 +213,15 @@ def time_spin(f, n, g, steps: int):
         res[f"{label}_ms_per_eval"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
     f.enable_timing(True)
     for _ in range(steps):
-        f.spin_async(*ins, outs, e)
-    ms, cnt = f.read_timing()["spin"]
+        f.spin_potential_async(*ins, vu, vd, e)
+    st = f.read_timing()
     f.enable_timing(False)
+    ms, cnt = st["spin"]
     res["conversion_ms_per_eval"] = round(ms / steps, 4)
     res["conversion_launches"] = cnt
+    res["divergence_ms_per_eval"] = round(sum(st[k][0] for k in ("div_z", "div_y", "div_x")) / steps, 4)
     res["E"] = float(e.item())
-    del ins, outs, sigma
+    del ins, vu, vd, v
     torch.cuda.empty_cache()
     return res
 
