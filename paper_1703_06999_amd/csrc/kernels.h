@@ -85,6 +85,7 @@ __device__ __forceinline__ void nt_store(Quad<float>* p, Quad<float> v) {
 __device__ __forceinline__ double nt_load(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void nt_store(double* p, double v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void nt_store(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(unsigned char* p, unsigned char v) { __builtin_nontemporal_store(v, p); }
 template <bool NT, typename V>
 __device__ __forceinline__ V ld(const V* p) {
   if constexpr (NT) return nt_load(p);
@@ -111,12 +112,15 @@ enum NtSite {
   kNtAsmState = 64,   // assembly: spline state
   kNtAsmOut = 128,    // assembly: dE/dn, dE/dsigma
   kNtDivZLoad = 256,  // z divergence pass: dE/dsigma and the gradient
-  kNtDivZStore = 512  // z divergence pass: its three outputs
+  kNtDivZStore = 512, // z divergence pass: its three outputs
+  kNtThetaIn = 1024,  // theta pass: density and gradient (or sigma)
+  kNtThetaSb = 2048   // theta pass: the spline interval bytes
 };
 // (at 512^3: FP64 theta, y and contraction 52.2 -> 50.7 ms/step with sites 1-16; FP32 30.4 -> 30.0
 // with sites 1-4, z divergence 1.09 -> 0.99 ms FP32 with its sites (FP64: 1.89 -> 1.96, so not
 // there).  Non-temporal reads of the assembly's half spectra, and of the FP32 inverse y pass's rows,
-// were slower: 7.25 -> 7.45 ms and 5.2 -> 6.6 ms, 4.2 -> 4.6 ms.)
+// were slower: 7.25 -> 7.45 ms and 5.2 -> 6.6 ms, 4.2 -> 4.6 ms.  The theta pass's inputs and
+// interval bytes and the assembly's state and outputs measured equal within the run-to-run spread.)
 #ifndef VDWXC_NT64
 #define VDWXC_NT64 (kNtThetaOut | kNtYfLoad | kNtYfStore | kNtYiLoad | kNtYiStore)
 #endif
@@ -390,13 +394,14 @@ struct PointIn {
   double n, s[3];
 };
 
+template <bool NT = false>
 __device__ __forceinline__ PointIn point_load(const double* __restrict__ nden, const double* __restrict__ sig,
                                               size_t idx, size_t N, bool from_grad) {
   PointIn r;
-  r.n = nden[idx];
-  r.s[0] = sig[idx];
-  r.s[1] = from_grad ? sig[N + idx] : 0.0;
-  r.s[2] = from_grad ? sig[2 * N + idx] : 0.0;
+  r.n = ld<NT>(&nden[idx]);
+  r.s[0] = ld<NT>(&sig[idx]);
+  r.s[1] = from_grad ? ld<NT>(&sig[N + idx]) : 0.0;
+  r.s[2] = from_grad ? ld<NT>(&sig[2 * N + idx]) : 0.0;
   return r;
 }
 
@@ -549,7 +554,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     in[r] = PointIn{0.0, {0.0, 0.0, 0.0}};
-    if (live) in[r] = point_load(nden, sig, pbase + 64 * r, N, SIGMA_FROM_GRAD);
+    if (live) in[r] = point_load<nt_site<T, kNtThetaIn>()>(nden, sig, pbase + 64 * r, N, SIGMA_FROM_GRAD);
   }
   __syncthreads();   // spline tables and twiddles in LDS (the point loads are in flight meanwhile)
   int pb[8];      // spline interval, 255: vacuum (theta = 0)
@@ -566,7 +571,7 @@ k_theta_zfwd512(const double* __restrict__ nden, const double* __restrict__ sig,
       q0_state(in[r].n, sv, g.zab, S.q, M, b, t, an, as);
       // the point's spline state for the inverse z pass: (t, n dq0/dn, n dq0/dsigma, b)
       st<nt_site<T, kNtThetaOut>()>(&state[pbase + 64 * r], Quad<T>{T(t), T(an), T(as), T(b < 0 ? 255 : b)});
-      sb[pbase + 64 * r] = (unsigned char)(b < 0 ? 255 : b);   // the interval alone, for the assembly
+      st<nt_site<T, kNtThetaSb>()>(&sb[pbase + 64 * r], (unsigned char)(b < 0 ? 255 : b));   // the interval alone, for the assembly
     }
     pb[r] = b < 0 ? 255 : b;
     pt[r] = T(t);
