@@ -1259,12 +1259,13 @@ struct SpinQ0 {
 __device__ __forceinline__ SpinQ0 spin_q0(double nu, double nd, double su, double sd, double zab) {
   SpinQ0 r;
   const double n = nu + nd, inv_n = 1.0 / n;
-  double X = 0.0, dxs[2] = {0.0, 0.0}, dss[2] = {0.0, 0.0};
+  double X = 0.0, dxs[2] = {0.0, 0.0}, dss[2] = {0.0, 0.0}, ks[2] = {0.0, 0.0};
   const double ns[2] = {nu, nd}, ss[2] = {su, sd};
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     if (ns[c] > 0.0) {
       const double k = cbrt(6.0 * kPi * kPi * ns[c]);
+      ks[c] = k;
       const double inv_nk = 1.0 / (ns[c] * k);
       X += ns[c] * inv_n * k - (zab / 36.0) * ss[c] * inv_n * inv_nk;
       dxs[c] = (4.0 / 3.0) * k * inv_n + (zab / 27.0) * ss[c] * inv_n * inv_nk / ns[c];
@@ -1282,7 +1283,9 @@ __device__ __forceinline__ SpinQ0 spin_q0(double nu, double nd, double su, doubl
   // a true division: at n_dn = 0 it gives zeta = 1 exactly, where f' holds (1 - zeta)^(1/3) and a
   // rounded 1 - 2^-53 would add cbrt(1e-16) ~ 5e-6 to it
   const double z = (nu - nd) / n;
-  const double cu = cbrt(1.0 + z), cd = cbrt(1.0 - z);
+  // (1 +- zeta)^(1/3) = (2 n_s / n)^(1/3) = k_s / k_F (zero for an empty channel)
+  const double inv_kF = 1.0 / r.kF;
+  const double cu = ks[0] * inv_kF, cd = ks[1] * inv_kF;
   const double fden = 1.0 / (2.0 * cbrt(2.0) - 2.0);   // 1 / (2^(4/3) - 2)
   const double f = ((1.0 + z) * cu + (1.0 - z) * cd - 2.0) * fden;
   const double df = (4.0 / 3.0) * (cu - cd) * fden;
@@ -1317,13 +1320,13 @@ __device__ __forceinline__ double spin_sigma(const double* __restrict__ s, long 
 }
 
 // (n_up, n_dn, sigma_uu, sigma_dd) -> (n, sigma_eff) for the spin-paired pipeline (su, sd: the
-// sigmas, or with FROM_GRAD the gradients of n_up, n_dn).  A NaN input gives NaN in both (the
-// pipeline flags it).
+// sigmas, or with FROM_GRAD the gradients of n_up, n_dn; suu_out, sdd_out, when given, receive the
+// sigmas).  A NaN input gives NaN in both (the pipeline flags it).
 template <bool FROM_GRAD>
 __global__ void __launch_bounds__(kSpinThreads)
 k_spin_in(const double* __restrict__ nu, const double* __restrict__ nd, const double* __restrict__ su,
-          const double* __restrict__ sd, double* __restrict__ n_out, double* __restrict__ s_out, double zab,
-          long long npts) {
+          const double* __restrict__ sd, double* __restrict__ n_out, double* __restrict__ s_out,
+          double* __restrict__ suu_out, double* __restrict__ sdd_out, double zab, long long npts) {
   for (long long p = (long long)blockIdx.x * kSpinThreads + threadIdx.x; p < npts;
        p += (long long)gridDim.x * kSpinThreads) {
     const double a = spin_channel(nu[p]), b = spin_channel(nd[p]);
@@ -1338,6 +1341,10 @@ k_spin_in(const double* __restrict__ nu, const double* __restrict__ nd, const do
     }
     n_out[p] = n;
     s_out[p] = seff;
+    if (suu_out) {   // the sigmas formed from the gradients, for k_spin_out
+      suu_out[p] = sa;
+      sdd_out[p] = sb;
+    }
   }
 }
 

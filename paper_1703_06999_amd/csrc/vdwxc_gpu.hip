@@ -1042,7 +1042,7 @@ vdwxc_status run_spin(vdwxc_ctx* h, const Work& w, const double* nu, const doubl
   const int blocks = int(std::min<long long>(kSpinBlocks, (N + kSpinThreads - 1) / kSpinThreads));
   stage_begin(h, w);
   hipLaunchKernelGGL(k_spin_in<false>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, su, sd, dnd, dsd,
-                     h->geo.zab, N);
+                     nullptr, nullptr, h->geo.zab, N);
   stage_end(h, w, VDWXC_STAGE_SPIN);
   if (vdwxc_status st = run_partials(h, w, dnd, dsd, dnu, dsu, energy_dev); st != VDWXC_OK) return st;
   stage_begin(h, w);
@@ -1053,21 +1053,24 @@ vdwxc_status run_spin(vdwxc_ctx* h, const Work& w, const double* nu, const doubl
 }
 
 // Spin-polarised potentials: as run_spin with sigma_ss taken from the gradients, (n, sigma_eff) in
-// v_dn and the work memory's gradient buffer, the pipeline's partials in v_up and S, the spin
-// partials converted in place (dE/dsigma_uu in S, dE/dsigma_dd in G), then one spectral divergence
-// per spin: v_s = dE/dn_s - div(2 dE/dsigma_ss grad n_s).
+// v_dn and the work memory's gradient buffer G (sigma_uu, sigma_dd beside sigma_eff in G's other
+// two thirds), the pipeline's partials in v_up and S, the spin partials converted in place
+// (dE/dsigma_uu in S, dE/dsigma_dd in G), then one spectral divergence per spin:
+// v_s = dE/dn_s - div(2 dE/dsigma_ss grad n_s).
 template <typename T>
 void enqueue_spin_potential(vdwxc_ctx* h, const Work& w, const double* nu, const double* nd, const double* gu,
                             const double* gd, double* vu, double* vd, double* energy_dev, int blocks) {
   const long long N = (long long)h->n1 * h->n2 * h->n3;
   stage_begin(h, w);
-  hipLaunchKernelGGL(k_spin_in<true>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, gu, gd, vd, w.G,
-                     h->geo.zab, N);
+  double* suu = w.G + N;
+  double* sdd = w.G + 2 * N;
+  hipLaunchKernelGGL(k_spin_in<true>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, gu, gd, vd, w.G, suu,
+                     sdd, h->geo.zab, N);
   stage_end(h, w, VDWXC_STAGE_SPIN);
   enqueue_main<T>(h, w, vd, w.G, false, vu, w.S, energy_dev);
   stage_begin(h, w);
-  hipLaunchKernelGGL(k_spin_out<true>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, gu, gd, vu, vd, w.S,
-                     w.G, h->geo.zab, N);
+  hipLaunchKernelGGL(k_spin_out<false>, dim3(blocks), dim3(kSpinThreads), 0, h->stream, nu, nd, suu, sdd, vu, vd,
+                     w.S, w.G, h->geo.zab, N);
   stage_end(h, w, VDWXC_STAGE_SPIN);
   enqueue_divergence<T>(h, w, w.S, gu, vu);
   enqueue_divergence<T>(h, w, w.G, gd, vd);
